@@ -1,0 +1,133 @@
+/*
+ * libpaam -- batched worst-case response-time analysis of ROS 2 processing
+ * chains served by a priority-driven accelerator manager, on AMD gfx950.
+ *
+ * The analysis is the admission test of the paper's Sec. IV-F: Eq. (1)
+ * (H* = H + delta*epsilon), Lemma 1 / Eq. (2) (arrival bound
+ * mu(t) = ceil(t/T) + 1), Lemma 2 / Eq. (3) (per-segment handling time),
+ * Lemma 3 / Eq. (4) (per-chain handling time), their minimum, Theorem 1 /
+ * Eq. (6) (chain response time; Lemma 4 / Eq. (5) when a chain has no
+ * segment) and the end-to-end sum over sub-chains that closes the section.
+ * The problem statement follows Sec. II-C (callback and chain tuples,
+ * executors, priorities) and Sec. IV-C (buckets).
+ *
+ * Conventions
+ *  - Times are int64 nanoseconds.  PAAM_INF (INT64_MAX) marks a bound whose
+ *    recurrence exceeded its cap (cap_mult * D of the chain).
+ *  - Every device buffer is owned by the caller; the library never allocates
+ *    device memory.  *_bytes() report the sizes to provide.
+ *  - Calls that take a stream are asynchronous on it; outputs are valid after
+ *    the stream synchronises.  The stream argument is a hipStream_t (NULL is
+ *    the default stream).
+ *  - A missed deadline is a result, never an error.
+ *  - On failure a call returns a negative paam_status and
+ *    paam_last_error() (thread-local) describes it.
+ */
+#ifndef PAAM_H
+#define PAAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t paam_status;
+#define PAAM_OK 0
+#define PAAM_E_INVAL (-1) /* malformed input: null pointer, bad offsets/indices, D > T, ... */
+#define PAAM_E_RANGE (-2) /* a value outside the exactly representable range (times >= 2^36) */
+#define PAAM_E_NOMEM (-3) /* a caller buffer is smaller than its *_bytes() size */
+#define PAAM_E_HIP (-4)   /* a HIP runtime call failed; the message names it */
+#define PAAM_E_STATE (-5) /* no usable gfx950 device, or a handle in the wrong state */
+
+#define PAAM_INF INT64_MAX
+
+typedef void *paam_stream; /* a hipStream_t */
+
+/* Host CSR description of n_sets independent chain sets (Sec. II-C).
+ * Offsets are global and non-decreasing; per-set indices are set-local. */
+typedef struct {
+  int64_t n_sets;
+  const int64_t *set_chain_off; /* [n_sets+1] chains of a set */
+  const int64_t *set_exec_off;  /* [n_sets+1] executors of a set */
+  const int64_t *set_accel_off; /* [n_sets+1] accelerators of a set */
+  const int64_t *chain_cb_off;  /* [n_chains+1] callbacks of a chain, in precedence order */
+  const int64_t *cb_seg_off;    /* [n_callbacks+1] accelerator segments of a callback (eta_i) */
+  const int64_t *T;             /* [n_chains] period T_c > 0 */
+  const int64_t *D;             /* [n_chains] constrained deadline, 0 < D_c <= T_c */
+  const int32_t *prio;          /* [n_chains] chain priority, unique in a set, larger = higher */
+  const uint8_t *spin;          /* [n_chains] 1: busy-waits during its requests; 0: suspends */
+  const int64_t *E;             /* [n_callbacks] CPU WCET E_i */
+  const int16_t *exec;          /* [n_callbacks] set-local executor of the callback */
+  const int64_t *A;             /* [n_segments] accelerator segment WCET A_ij */
+  const int16_t *accel;         /* [n_segments] set-local accelerator of the segment (r_ij) */
+  const int16_t *exec_core;     /* [n_executors] CPU core of the executor */
+  const int32_t *exec_prio;     /* [n_executors] OS process priority, unique per core */
+  const int16_t *accel_buckets; /* [n_accels] number of buckets n >= 1 (Sec. IV-C) */
+  const int64_t *accel_eps;     /* [n_accels] per-request server overhead epsilon */
+  const int64_t *accel_kappa;   /* [n_accels] device preemption cost kappa */
+  const int64_t *eps_hop;       /* [n_sets] communication cost between consecutive sub-chains */
+} paam_chainset_host;
+
+typedef struct paam_chainset paam_chainset; /* opaque host handle of an uploaded batch */
+
+/* Size of the device arena paam_chainset_upload needs for this batch. */
+paam_status paam_chainset_bytes(const paam_chainset_host *h, size_t *arena_bytes);
+
+/* Validates the batch, derives its priority-independent structure
+ * (sub-chains = maximal runs of consecutive callbacks on one executor,
+ * executor order per core, reciprocals of the periods, a longest-first work
+ * order) and copies it into the caller's device arena (>= arena_bytes, 256-B
+ * aligned).  Blocks until the copy is done.  *out must be released with
+ * paam_chainset_free; the arena must outlive it.  Limits per set: 1..4096
+ * chains, 1..32 executors, 0..8 accelerators, 65535 sub-chains; every time
+ * below 2^36 ns (PAAM_E_RANGE otherwise). */
+paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, size_t arena_bytes,
+                                 paam_stream stream, paam_chainset **out);
+void paam_chainset_free(paam_chainset *cs);
+
+/* Counts of an uploaded batch: n_sets, n_chains, n_callbacks, n_segments,
+ * n_subchains, and the per-set maxima of chains, sub-chains, segments. */
+paam_status paam_chainset_info(const paam_chainset *cs, int64_t info[8]);
+
+#define PAAM_BLOCK_SAFE 0  /* blocking by an LP callback includes its accelerator handling */
+#define PAAM_BLOCK_PAPER 1 /* blocking = max E_j of LP callbacks, as printed in Eq. (5)/(6) */
+#define PAAM_BOUND_MIN 0   /* H = min(Lemma 2 summed over segments, Lemma 3) */
+#define PAAM_BOUND_L2 1    /* Lemma 2 only */
+#define PAAM_BOUND_L3 2    /* Lemma 3 only */
+
+typedef struct {
+  int32_t blocking;      /* PAAM_BLOCK_* */
+  int32_t cap_mult;      /* >= 1: an iterate above cap_mult * D of its chain makes it PAAM_INF */
+  int32_t util_permille; /* >= 0: every E and A enters as floor(x * util_permille / 1000) */
+  int32_t full;          /* 1: every chain's bound; 0: verdict only, stop a set at its first miss */
+  int32_t bound;         /* PAAM_BOUND_* */
+  int32_t waves_per_cu;  /* persistent waves per compute unit; 0 = tuned default */
+} paam_wcrt_opts;
+
+/* Workspace for paam_wcrt_batch (device, caller-owned, 256-B aligned). */
+paam_status paam_wcrt_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, size_t *ws_bytes);
+
+/* Analyses every set of the batch (Sec. IV-F, Theorem 1 and the end-to-end
+ * sum).  Outputs, all device pointers:
+ *   set_sched [n_sets]   1 if every chain meets its deadline
+ *   set_worst [n_sets]   set-local chain with the largest R/D (ties: lowest
+ *                        index); -1 for an unschedulable set when !full
+ *   set_worst_R [n_sets] that chain's bound; PAAM_INF when set_worst is -1
+ *   chain_R [n_chains]   end-to-end bound of every chain (PAAM_INF past its
+ *                        cap); required when full, ignored (may be NULL) if not */
+paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, int8_t *set_sched,
+                            int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R, void *d_ws,
+                            size_t ws_bytes, paam_stream stream);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *paam_last_error(void);
+
+/* Library version string. */
+const char *paam_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

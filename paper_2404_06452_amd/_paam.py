@@ -1,0 +1,194 @@
+"""ctypes binding of libpaam (include/paam.h): argument marshalling only.
+
+Every step of the analysis runs in the HIP kernels of libpaam.so.  PyTorch
+supplies device memory (the arena, workspaces, outputs) and streams.  There is
+no fallback: if the library is missing or the device is not gfx950 the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBPAAM = os.path.join(PKG, "libpaam.so")
+
+PAAM_OK = 0
+PAAM_INF = np.iinfo(np.int64).max
+PAAM_BLOCK_SAFE, PAAM_BLOCK_PAPER = 0, 1
+PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
+
+EXPORTED = (
+    "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
+    "paam_wcrt_bytes", "paam_wcrt_batch", "paam_last_error", "paam_version",
+)
+
+
+class PaamError(RuntimeError):
+    pass
+
+
+class paam_chainset_host(ctypes.Structure):
+    _fields_ = [("n_sets", ctypes.c_int64)] + [(n, ctypes.c_void_p) for n in (
+        "set_chain_off", "set_exec_off", "set_accel_off", "chain_cb_off", "cb_seg_off", "T", "D",
+        "prio", "spin", "E", "exec", "A", "accel", "exec_core", "exec_prio", "accel_buckets",
+        "accel_eps", "accel_kappa", "eps_hop")]
+
+
+class paam_wcrt_opts(ctypes.Structure):
+    _fields_ = [("blocking", ctypes.c_int32), ("cap_mult", ctypes.c_int32),
+                ("util_permille", ctypes.c_int32), ("full", ctypes.c_int32),
+                ("bound", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libpaam.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPAAM):
+            raise PaamError("libpaam.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIBPAAM)
+        P, S = ctypes.c_void_p, ctypes.c_size_t
+        L.paam_chainset_bytes.argtypes = [ctypes.POINTER(paam_chainset_host), ctypes.POINTER(S)]
+        L.paam_chainset_upload.argtypes = [ctypes.POINTER(paam_chainset_host), P, S, P,
+                                           ctypes.POINTER(P)]
+        L.paam_chainset_free.argtypes = [P]
+        L.paam_chainset_free.restype = None
+        L.paam_chainset_info.argtypes = [P, P]
+        L.paam_wcrt_bytes.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), ctypes.POINTER(S)]
+        L.paam_wcrt_batch.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P, S, P]
+        L.paam_last_error.argtypes = []
+        L.paam_last_error.restype = ctypes.c_char_p
+        L.paam_version.argtypes = []
+        L.paam_version.restype = ctypes.c_char_p
+        for f in ("paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_info",
+                  "paam_wcrt_bytes", "paam_wcrt_batch"):
+            getattr(L, f).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str) -> None:
+    if status != PAAM_OK:
+        msg = lib().paam_last_error().decode(errors="replace")
+        raise PaamError("%s failed (%d): %s" % (what, status, msg))
+
+
+_HOST_DTYPES = {
+    "set_chain_off": np.int64, "set_exec_off": np.int64, "set_accel_off": np.int64,
+    "chain_cb_off": np.int64, "cb_seg_off": np.int64, "T": np.int64, "D": np.int64,
+    "prio": np.int32, "spin": np.uint8, "E": np.int64, "exec": np.int16, "A": np.int64,
+    "accel": np.int16, "exec_core": np.int16, "exec_prio": np.int32, "accel_buckets": np.int16,
+    "accel_eps": np.int64, "accel_kappa": np.int64, "eps_hop": np.int64,
+}
+
+
+class HostBatch:
+    """paam_chainset_host over contiguous numpy copies of a CSR batch."""
+
+    def __init__(self, cs):
+        self.arrays = {k: np.ascontiguousarray(getattr(cs, k), dtype=t)
+                       for k, t in _HOST_DTYPES.items()}
+        self.n_sets = int(cs.n_sets)
+        self.struct = paam_chainset_host(
+            n_sets=self.n_sets, **{k: v.ctypes.data for k, v in self.arrays.items()})
+
+
+def _stream_ptr(stream) -> int | None:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class Chainset:
+    """An uploaded batch: the device arena (a torch uint8 tensor) and the
+    opaque library handle."""
+
+    def __init__(self, cs, device="cuda:0", stream=None):
+        import torch
+        self.host = HostBatch(cs)
+        n = ctypes.c_size_t(0)
+        check(lib().paam_chainset_bytes(ctypes.byref(self.host.struct), ctypes.byref(n)),
+              "paam_chainset_bytes")
+        self.arena = torch.empty(int(n.value), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p(0)
+        check(lib().paam_chainset_upload(ctypes.byref(self.host.struct), self.arena.data_ptr(),
+                                         int(n.value), _stream_ptr(stream), ctypes.byref(h)),
+              "paam_chainset_upload")
+        self.handle = h
+        self.device = device
+        info = np.zeros(8, np.int64)
+        check(lib().paam_chainset_info(self.handle, info.ctypes.data), "paam_chainset_info")
+        (self.n_sets, self.n_chains, self.n_callbacks, self.n_segments, self.n_subchains,
+         self.max_chains, self.max_subchains, self.max_segments) = (int(v) for v in info)
+
+    def free(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().paam_chainset_free(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def wcrt_opts(blocking=PAAM_BLOCK_SAFE, cap_mult=1, util_permille=1000, full=True,
+              bound=PAAM_BOUND_MIN, waves_per_cu=0) -> paam_wcrt_opts:
+    return paam_wcrt_opts(blocking=blocking, cap_mult=cap_mult, util_permille=util_permille,
+                          full=1 if full else 0, bound=bound, waves_per_cu=waves_per_cu)
+
+
+def paam_wcrt_bytes(cs: Chainset, opts: paam_wcrt_opts) -> int:
+    n = ctypes.c_size_t(0)
+    check(lib().paam_wcrt_bytes(cs.handle, ctypes.byref(opts), ctypes.byref(n)), "paam_wcrt_bytes")
+    return int(n.value)
+
+
+class WcrtOut:
+    def __init__(self, cs: Chainset, full: bool):
+        import torch
+        d = cs.device
+        self.set_sched = torch.empty(cs.n_sets, dtype=torch.int8, device=d)
+        self.set_worst = torch.empty(cs.n_sets, dtype=torch.int32, device=d)
+        self.set_worst_R = torch.empty(cs.n_sets, dtype=torch.int64, device=d)
+        self.chain_R = torch.empty(max(cs.n_chains, 1), dtype=torch.int64, device=d) if full else None
+
+
+def paam_wcrt_batch(cs: Chainset, opts: paam_wcrt_opts, out: WcrtOut, ws, stream=None) -> None:
+    check(lib().paam_wcrt_batch(cs.handle, ctypes.byref(opts), out.set_sched.data_ptr(),
+                                out.set_worst.data_ptr(), out.set_worst_R.data_ptr(),
+                                _dev_ptr(out.chain_R), ws.data_ptr(), ws.numel(),
+                                _stream_ptr(stream)),
+          "paam_wcrt_batch")
+
+
+def workspace(nbytes: int, device="cuda:0"):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def wcrt(cs: Chainset, stream=None, **kw) -> dict:
+    """One analysis of an uploaded batch; returns host numpy arrays."""
+    import torch
+    o = wcrt_opts(**kw)
+    out = WcrtOut(cs, bool(o.full))
+    ws = workspace(paam_wcrt_bytes(cs, o), cs.device)
+    paam_wcrt_batch(cs, o, out, ws, stream)
+    torch.cuda.synchronize()
+    res = {"sched": out.set_sched.cpu().numpy(), "worst": out.set_worst.cpu().numpy(),
+           "worst_R": out.set_worst_R.cpu().numpy()}
+    if out.chain_R is not None:
+        res["chain_R"] = out.chain_R.cpu().numpy()[:cs.n_chains]
+    return res

@@ -1,0 +1,95 @@
+// Internal device layout of an uploaded batch (libpaam only).
+//
+// Everything that does not depend on priorities or on the utilisation scale
+// is derived once on the host at upload: sub-chains (maximal runs of
+// consecutive callbacks of a chain on one executor, the sub-chains of the
+// end-to-end sum in Sec. IV-F), the solving order of executors on each core,
+// the reciprocals of the periods, and a longest-first work order.  The
+// kernels derive the rest (A*, buckets, blocking, Lemma 2/3, Theorem 1) per
+// launch, because it changes with the utilisation level and the candidate
+// priority order.
+#pragma once
+#include <stdint.h>
+
+#include "paam.h"
+
+namespace paam {
+
+constexpr int kWave = 64;
+constexpr int kMaxExec = 32;     // executors per set (hpp masks are 32-bit)
+constexpr int kMaxAccel = 8;     // accelerators per set (accelerator masks are 8-bit)
+constexpr int kMaxChains = 4096; // chains per set
+constexpr int kMaxRuns = 65535;  // sub-chains per set
+constexpr int64_t kTimeLimit = int64_t(1) << 36;  // every input time is below 2^36 ns
+
+// Pointers into the caller's device arena.  Offsets are global (int64);
+// indices stored per chain, callback, segment or sub-chain are set-local.
+struct DevBatch {
+  int64_t n_sets, n_chains, n_cbs, n_segs, n_runs;
+  // sets
+  const int64_t *set_chain_off, *set_cb_off, *set_seg_off, *set_run_off, *set_exec_off,
+      *set_accel_off;          // [n_sets+1]
+  const int64_t *eps_hop;      // [n_sets]
+  const int64_t *work_order;   // [n_sets] sets by decreasing estimated cost
+  // chains
+  const int64_t *T, *D;        // [n_chains]
+  const double *Kd;            // [n_chains] 2T - 1
+  const double *rcp;           // [n_chains] 1/T rounded towards +inf
+  const int16_t *rank0;        // [n_chains] rank under the uploaded priorities, 0 = highest
+  const int32_t *chain_nrun;   // [n_chains] sub-chains of the chain
+  const uint8_t *spin;         // [n_chains]
+  // callbacks
+  const int64_t *E;            // [n_cbs]
+  const int64_t *cb_seg_off;   // [n_cbs+1] global segment offsets
+  // segments
+  const int64_t *A;            // [n_segs]
+  const int16_t *seg_accel;    // [n_segs]
+  const int16_t *seg_chain;    // [n_segs]
+  // sub-chains, set-local ids in chain order
+  const int16_t *run_chain;    // [n_runs]
+  const int16_t *run_exec;     // [n_runs]
+  const int32_t *run_cb_lo, *run_cb_hi;  // [n_runs] set-local callback range
+  const int32_t *exec_runs;    // [n_runs] per set: sub-chain ids grouped by executor
+  // executors
+  const int32_t *er_off, *er_cnt;  // [n_exec] position/count of the executor's group
+  const uint32_t *hpx_mask;        // [n_exec] executors of the same core with higher process priority
+  const int16_t *exec_seq;         // [n_exec] per set: executors in solving order
+  // accelerators
+  const int32_t *buckets;          // [n_accels]
+  const int64_t *aeps, *akappa;    // [n_accels]
+  // per-set maxima over the batch
+  int32_t max_C, max_X, max_NA, max_runs, max_segs, max_runs_exec;
+};
+
+}  // namespace paam
+
+struct paam_chainset {
+  paam::DevBatch dev;
+  size_t arena_bytes;
+  int64_t n_exec, n_accel;
+};
+
+namespace paam {
+
+struct WcrtLaunch {
+  DevBatch b;
+  paam_wcrt_opts o;
+  int8_t *set_sched;
+  int32_t *set_worst;
+  int64_t *set_worst_R;
+  int64_t *chain_R;
+  unsigned long long *counter;  // work queue head, zeroed before the launch
+  unsigned char *scratch;       // per persistent wave
+  size_t scratch_stride;        // bytes per wave
+  size_t lds_bytes;
+  int grid;
+};
+
+// Scratch and LDS sizes for one wave analysing one set at a time.
+size_t wave_scratch_bytes(const DevBatch &b);
+size_t wave_lds_bytes(const DevBatch &b);
+
+// Launches (defined in paam_kernels.hip); return a hipError_t as int.
+int launch_wcrt(const WcrtLaunch &L, void *stream);
+
+}  // namespace paam

@@ -1,0 +1,87 @@
+"""The C-ABI boundary, checked without a GPU: the library loads, exports every
+entry point include/paam.h declares, and the product path is independent of
+the oracle (neither imports, includes or links the other)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "paam.h")
+PKG = os.path.join(ROOT, "paper_2404_06452_amd")
+
+
+def declared_entry_points():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(paam_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_entry_points()
+    for n in ("paam_chainset_upload", "paam_wcrt_batch", "paam_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2404_06452_amd import _paam
+    if not os.path.exists(_paam.LIBPAAM):
+        pytest.fail("libpaam.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(_paam.LIBPAAM)
+    missing = [n for n in declared_entry_points() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_paam.EXPORTED) <= set(declared_entry_points())
+    assert b"gfx950" in _paam.lib().paam_version()
+
+
+def test_errors_are_reported_without_a_device():
+    from paper_2404_06452_amd import _paam
+    L = _paam.lib()
+    n = ctypes.c_size_t(0)
+    assert L.paam_chainset_bytes(None, ctypes.byref(n)) == -1
+    assert b"null" in L.paam_last_error()
+
+
+def test_bytes_query_validates_the_problem_statement():
+    import numpy as np
+    from paper_2404_06452_amd import _paam, chaingen
+    cs = chaingen.generate("small", 4)
+    hb = _paam.HostBatch(cs)
+    n = ctypes.c_size_t(0)
+    assert _paam.lib().paam_chainset_bytes(ctypes.byref(hb.struct), ctypes.byref(n)) == 0
+    assert n.value > cs.nbytes()
+    bad = chaingen.generate("small", 4)
+    bad.D = bad.T + 1  # D > T violates the constrained-deadline model
+    hb = _paam.HostBatch(bad)
+    assert _paam.lib().paam_chainset_bytes(ctypes.byref(hb.struct), ctypes.byref(n)) == -1
+    assert b"D <= T" in _paam.lib().paam_last_error()
+    big = chaingen.generate("small", 4)
+    big.T = big.T.copy()
+    big.T[0] = 1 << 37
+    big.D = big.T.copy()
+    hb = _paam.HostBatch(big)
+    assert _paam.lib().paam_chainset_bytes(ctypes.byref(hb.struct), ctypes.byref(n)) == -2
+    dup = chaingen.generate("small", 4)
+    dup.prio = dup.prio.copy()
+    dup.prio[1] = dup.prio[0]
+    hb = _paam.HostBatch(dup)
+    assert _paam.lib().paam_chainset_bytes(ctypes.byref(hb.struct), ctypes.byref(n)) == -1
+
+
+def _sources(pattern_root, exts):
+    out = []
+    for ext in exts:
+        out += glob.glob(os.path.join(pattern_root, "**", "*" + ext), recursive=True)
+    return out
+
+
+def test_product_and_oracle_share_no_code():
+    for path in _sources(PKG, (".py", ".cpp", ".hip", ".h", ".c")):
+        text = open(path).read()
+        assert "oracle" not in re.sub(r"#.*|//.*|/\*.*?\*/|\"\"\".*?\"\"\"", "", text, flags=re.S), path
+    for path in _sources(os.path.join(ROOT, "oracle"), (".py", ".c", ".h")):
+        text = open(path).read()
+        assert "paper_2404_06452_amd" not in text and "paam.h" not in text, path
+        assert "paam_internal" not in text, path

@@ -1,0 +1,142 @@
+"""GPU parity of paam_wcrt_batch against the CPU oracle, bit-exact (int64).
+
+The analysis is integer arithmetic, so every bound, verdict and worst chain
+must be identical to the oracle's on the same seeded inputs."""
+import glob
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_06452_amd import chaingen
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "ex_*.json")))
+
+
+@pytest.fixture(scope="module")
+def paam():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_06452_amd import _paam
+    return _paam
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+OPTS = [
+    dict(full=True),
+    dict(full=False),
+    dict(full=True, blocking=1),
+    dict(full=True, cap_mult=2),
+    dict(full=True, bound=1),
+    dict(full=True, bound=2),
+    dict(full=False, cap_mult=3, blocking=1),
+]
+
+
+def compare(paam, cs, dev, opts, label):
+    o = dict(opts)
+    g = paam.wcrt(dev, **o)
+    r = oracle.wcrt(cs, threads=8, **o)
+    assert np.array_equal(g["sched"], r["sched"]), label
+    assert np.array_equal(g["worst"], r["worst"]), label
+    assert np.array_equal(g["worst_R"], r["worst_R"]), label
+    if o.get("full", True):
+        bad = np.nonzero(g["chain_R"] != r["chain_R"])[0]
+        assert bad.size == 0, (label, bad[:10], g["chain_R"][bad[:10]], r["chain_R"][bad[:10]])
+    return g
+
+
+def test_worked_examples_on_gpu(paam):
+    sets, expect = [], []
+    for p in GOLDEN:
+        fx = json.load(open(p))
+        sets.append(fx["set"])
+    cs = chaingen.from_sets(sets)
+    dev = paam.Chainset(cs)
+    note("golden: %d sets" % cs.n_sets)
+    for opts in OPTS:
+        compare(paam, cs, dev, opts, ("golden", opts))
+
+
+@pytest.mark.parametrize("preset", ["small", "small_overheads"])
+def test_small_config_all_options(paam, preset):
+    cs = chaingen.generate(preset, 1000)
+    dev = paam.Chainset(cs)
+    for opts in OPTS:
+        note("%s %s" % (preset, opts))
+        compare(paam, cs, dev, opts, (preset, opts))
+
+
+def test_schedulable_mix_and_multi_accelerator(paam):
+    p = chaingen.PRESETS["small"].replace(seed=77, chains=(1, 9), cbs=(1, 4), n_exec=5,
+                                          util=(0.02, 0.5), pseg=(0.2, 0.8), frac=(0.05, 0.9),
+                                          T=(20.0, 4000.0), n_accel=3, max_seg_per_cb=3,
+                                          n_buckets=3, eps=2, kappa=1, eps_hop=1)
+    cs = chaingen.generate(p, 3000)
+    dev = paam.Chainset(cs)
+    for opts in OPTS:
+        note("mix %s" % opts)
+        g = compare(paam, cs, dev, opts, ("mix", opts))
+    assert 0.05 < g["sched"].mean() < 0.95
+
+
+@pytest.mark.parametrize("level", [100, 350, 600, 950])
+def test_sweep_sets_at_levels(paam, level):
+    cs = chaingen.generate("sweep", 1500)
+    dev = paam.Chainset(cs)
+    for full in (True, False):
+        note("sweep level %d full=%s" % (level, full))
+        compare(paam, cs, dev, dict(full=full, util_permille=level), ("sweep", level, full))
+
+
+def test_search_shaped_sets(paam):
+    for U in ((0.5, 0.9), (0.02, 0.2)):
+        cs = chaingen.generate(chaingen.PRESETS["search"].replace(util=U), 2000)
+        dev = paam.Chainset(cs)
+        for opts in (dict(full=True), dict(full=False), dict(full=True, cap_mult=2)):
+            note("search-shaped %s %s" % (U, opts))
+            compare(paam, cs, dev, opts, ("search", U, opts))
+
+
+def test_large_sets_sample(paam):
+    cs = chaingen.generate("large", 12)
+    dev = paam.Chainset(cs)
+    for opts in (dict(full=True), dict(full=False), dict(full=True, cap_mult=2)):
+        note("large %s" % opts)
+        compare(paam, cs, dev, opts, ("large", opts))
+
+
+def test_empty_and_degenerate_batches(paam):
+    # a single one-callback chain, a chain with zero WCET, one executor
+    sets = [
+        {"chains": [{"T": 10, "D": 10, "prio": 1, "cbs": [{"E": 0, "exec": 0, "segs": []}]}],
+         "exec_core": [0], "exec_prio": [1]},
+        {"chains": [{"T": 10, "D": 5, "prio": 1, "cbs": [{"E": 3, "exec": 0, "segs": [(2, 0)]}]},
+                    {"T": 7, "D": 7, "prio": 2, "cbs": [{"E": 0, "exec": 1, "segs": [(0, 0)]}]}],
+         "exec_core": [0, 0], "exec_prio": [1, 2]},
+    ]
+    cs = chaingen.from_sets(sets)
+    dev = paam.Chainset(cs)
+    for opts in OPTS:
+        compare(paam, cs, dev, opts, ("degenerate", opts))
+
+
+def test_repeatable_and_schedule_independent(paam):
+    """Identical results across launches and persistent-grid sizes (a data
+    race or an order-dependent iteration would show up here)."""
+    cs = chaingen.generate("sweep", 3000, set_begin=5000)
+    dev = paam.Chainset(cs)
+    ref = paam.wcrt(dev, full=True, util_permille=400)
+    for w in (1, 2, 4, 16):
+        g = paam.wcrt(dev, full=True, util_permille=400, waves_per_cu=w)
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (w, k)
