@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark: batched worst-case response-time analyses per second on one GPU.
+
+Workload (the paper's Sec. IV-F analysis over synthetic chain sets): 1,000,000
+chain sets of 4-64 chains x 2-12 callbacks, 4 executors (pairs share a core),
+one accelerator, periods log-uniform over 10-1000 ms, segment share per set
+U(10, 60) % of the callbacks with 5-80 % of the callback WCET; drawn at total
+utilisation 1 and analysed at the 18 utilisation levels 0.10, 0.15, ..., 0.95.
+One step = the whole sweep: 18 launches of the analysis (one per level, every
+chain's end-to-end bound, cap = deadline), captured once as a HIP graph and
+replayed.  Inputs are resident in HBM before the timed region.
+
+Printed JSON line: value = analyses per second (18 M per step); roofline of
+the analysis kernel (ALU-bound: interference terms per second against the
+fp64 issue rate); cpu_baseline = the CPU oracle, single-threaded, on a sample
+of the same sweep, whose outputs are also compared bit-exactly with the GPU's.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak interference-term rate: a term is one fp64 add, mul, floor and fma on a
+# lane; 256 CUs x 64 lanes x 2.4 GHz issue 39.3 T fp64 lane-ops/s (the
+# published 78.6 TFLOP/s fp64 vector rate counts an fma as 2).
+FP64_LANE_OPS = 256 * 64 * 2.4e9
+OPS_PER_TERM = 4
+PEAK_TERMS = FP64_LANE_OPS / OPS_PER_TERM
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sets", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=1000, help="sets per level for the oracle")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the analysis shards across GPUs by set range with no "
+              "exchange, but this build runs and reports a single MI355X only (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2404_06452_amd import _paam, chaingen
+
+    levels = list(chaingen.SWEEP_LEVELS)
+    t0 = time.perf_counter()
+    cs = chaingen.generate("sweep", args.sets)
+    log("generated %d sets (%d chains, %d callbacks, %d segments) in %.1f s" % (
+        cs.n_sets, cs.n_chains, cs.n_callbacks, cs.n_segments, time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    dev = _paam.Chainset(cs, device="cuda:0")
+    log("uploaded %.2f GB arena, %d sub-chains in %.1f s" % (
+        dev.arena.numel() / 1e9, dev.n_subchains, time.perf_counter() - t0))
+
+    stream = torch.cuda.Stream()
+    opts = [_paam.wcrt_opts(full=True, util_permille=u, waves_per_cu=args.waves_per_cu)
+            for u in levels]
+    ws = _paam.workspace(max(_paam.paam_wcrt_bytes(dev, o) for o in opts))
+    outs = [_paam.WcrtOut(dev, True) for _ in levels]
+
+    def sweep(s):
+        for o, out in zip(opts, outs):
+            _paam.paam_wcrt_batch(dev, o, out, ws, s)
+
+    graph = None
+    with torch.cuda.stream(stream):
+        sweep(stream)  # eager run: also the reference for the graph replays
+    torch.cuda.synchronize()
+    eager = [(o.set_sched.clone(), o.chain_R.clone()) for o in outs]
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            sweep(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+
+    def step():
+        if graph is not None:
+            graph.replay()
+        else:
+            sweep(stream)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+    torch.cuda.synchronize()
+    # graph replays must reproduce the eager results exactly
+    for (s0, r0), o in zip(eager, outs):
+        assert torch.equal(s0, o.set_sched) and torch.equal(r0, o.chain_R), "graph replay differs"
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for a, b in ev:
+            a.record(stream)
+            step()
+            b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    analyses = cs.n_sets * len(levels)
+    value = analyses * args.steps / wall
+    launch_ms = float(np.mean(step_ms)) / len(levels)  # one analysis launch (+ its queue reset)
+    log("%.1f ms/step (events %.1f), %.3g analyses/s" % (ms_per_step, np.mean(step_ms), value))
+
+    # verdict-only mode (stops a set at its first missed deadline), one sweep
+    vopts = [_paam.wcrt_opts(full=False, util_permille=u) for u in levels]
+    vout = _paam.WcrtOut(dev, False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for o in vopts:
+            _paam.paam_wcrt_batch(dev, o, vout, ws, stream)
+    torch.cuda.synchronize()
+    verdict_rate = analyses / (time.perf_counter() - t1)
+
+    # CPU oracle on a bounded sample of the same sweep (single thread), and
+    # bit-exact comparison of the GPU outputs on that sample
+    import oracle
+    n_s = min(args.cpu_sample, cs.n_sets)
+    sample = cs.subset(range(n_s))
+    terms_per_level, cpu_time, mism = [], 0.0, 0
+    sched_rate = []
+    for li, u in enumerate(levels):
+        t1 = time.perf_counter()
+        r = oracle.wcrt(sample, full=True, util_permille=u)
+        cpu_time += time.perf_counter() - t1
+        terms_per_level.append(float(r["terms"].mean()))
+        g_sched = outs[li].set_sched[:n_s].cpu().numpy()
+        g_R = outs[li].chain_R[:int(sample.n_chains)].cpu().numpy()
+        mism += int(np.sum(g_sched != r["sched"])) + int(np.sum(g_R != r["chain_R"]))
+        sched_rate.append(float(outs[li].set_sched.float().mean().item()))
+    cpu_rate = n_s * len(levels) / cpu_time
+    log("oracle: %d analyses in %.1f s; mismatches %d" % (n_s * len(levels), cpu_time, mism))
+
+    # roofline: algorithmic terms per launch (oracle count per analysis on the
+    # sample x sets per launch) over the average launch duration
+    terms_per_launch = float(np.mean(terms_per_level)) * cs.n_sets
+    achieved = terms_per_launch / (launch_ms * 1e-3)
+    line = {
+        "metric": "WCRT analyses/sec bit-exact",
+        "value": value,
+        "unit": "analyses/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "utilisation sweep: %d chain sets x %d levels (0.10-0.95), 4-64 chains x "
+                        "2-12 callbacks, 4 executors, 1 accelerator; every chain's end-to-end "
+                        "bound, cap = deadline" % (cs.n_sets, len(levels)),
+            "n_sets": cs.n_sets, "levels": len(levels), "analyses_per_step": analyses,
+            "chains": cs.n_chains, "callbacks": cs.n_callbacks, "segments": cs.n_segments,
+            "subchains": dev.n_subchains, "hip_graph": graph is not None,
+            "parallelism": "single GPU",
+        },
+        "parity": {"sampled_analyses": n_s * len(levels), "mismatches": mism,
+                   "compared": "set verdicts and every chain bound vs the CPU oracle"},
+        "verdict_mode_analyses_per_s": verdict_rate,
+        "schedulable_fraction_by_level": dict(zip([u / 1000 for u in levels], sched_rate)),
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e9,
+            "peak": PEAK_TERMS / 1e9,
+            "unit": "Gterm/s",
+            "frac": achieved / PEAK_TERMS,
+            "traffic": None,
+            "kernel": "wcrt_kernel",
+            "avg_launch_ms": launch_ms,
+            "terms_per_analysis": float(np.mean(terms_per_level)),
+        },
+        "cpu_baseline": {
+            "value": cpu_rate, "unit": "analyses/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d sets of the same batch at all %d levels (%d analyses), full "
+                      "mode" % (n_s, len(levels), n_s * len(levels)),
+        },
+    }
+    print(json.dumps(line), flush=True)
+    if mism:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()
