@@ -121,6 +121,43 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
                             int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R, void *d_ws,
                             size_t ws_bytes, paam_stream stream);
 
+/* ---------------- priority-order search (candidate orders) ----------------
+ * Candidate 0 of a set is its uploaded order (chains by decreasing prio).
+ * Candidate k >= 1 is candidate k-1 with two positions swapped: with u1, u2
+ * the outputs 2k-2 and 2k-1 of the SplitMix64 stream of the set (state
+ * starting at mix(seed + G*(set+1)), advancing by G = 0x9E3779B97F4A7C15 per
+ * output, mix = the SplitMix64 output function), positions i = u1 mod C and
+ * j = (i + 1 + u2 mod (C-1)) mod C swap.  A candidate is feasible when the
+ * analysis (verdict mode) finds every chain within its deadline, i.e. the
+ * admission test of Sec. IV-F accepts the set under that priority
+ * assignment (Sec. II-C: static, unique chain priorities). */
+typedef struct {
+  int32_t n_cand;        /* candidate orders per set, 1..65536 */
+  int32_t guided;        /* 0: plain search in index order; 1: lowest score first */
+  int32_t top_k;         /* guided: candidates analysed in score order, 1..n_cand */
+  int32_t fallback;      /* guided: 1 = plain search over the rest when none of the top_k is feasible */
+  uint64_t seed;         /* seed of the swap walk */
+  const float *d_scores; /* guided: [n_sets*n_cand] device scores (predicted max R/D); else NULL */
+  paam_wcrt_opts wcrt;   /* analysis options; full is ignored (verdict mode) */
+} paam_search_opts;
+
+/* Workspace for paam_priority_search (device, caller-owned, 256-B aligned). */
+paam_status paam_search_bytes(const paam_chainset *cs, const paam_search_opts *o, size_t *ws_bytes);
+
+/* Searches every set for a feasible candidate order.  Outputs (device):
+ *   found [n_sets]      plain: the smallest feasible k; guided: the first
+ *                       feasible candidate in score order among the top_k
+ *                       (ties: lower k), then, with fallback, the smallest
+ *                       feasible k among the others; -1 if none; -2 if the
+ *                       analysis hit its iteration guard
+ *   n_exact [n_sets]    exact analyses run for the set
+ *   found_prio [n_chains] (may be NULL) the found order as priorities
+ *                       (C - position, larger = higher); untouched for sets
+ *                       with found < 0 */
+paam_status paam_priority_search(const paam_chainset *cs, const paam_search_opts *o,
+                                 int32_t *found, int32_t *n_exact, int32_t *found_prio, void *d_ws,
+                                 size_t ws_bytes, paam_stream stream);
+
 /* Thread-local description of the last failure ("" if none). */
 const char *paam_last_error(void);
 

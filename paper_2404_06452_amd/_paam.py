@@ -22,7 +22,8 @@ PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
 
 EXPORTED = (
     "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
-    "paam_wcrt_bytes", "paam_wcrt_batch", "paam_last_error", "paam_version",
+    "paam_wcrt_bytes", "paam_wcrt_batch", "paam_search_bytes", "paam_priority_search",
+    "paam_last_error", "paam_version",
 )
 
 
@@ -41,6 +42,12 @@ class paam_wcrt_opts(ctypes.Structure):
     _fields_ = [("blocking", ctypes.c_int32), ("cap_mult", ctypes.c_int32),
                 ("util_permille", ctypes.c_int32), ("full", ctypes.c_int32),
                 ("bound", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+
+
+class paam_search_opts(ctypes.Structure):
+    _fields_ = [("n_cand", ctypes.c_int32), ("guided", ctypes.c_int32), ("top_k", ctypes.c_int32),
+                ("fallback", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("d_scores", ctypes.c_void_p), ("wcrt", paam_wcrt_opts)]
 
 
 _lib = None
@@ -62,12 +69,15 @@ def lib():
         L.paam_chainset_info.argtypes = [P, P]
         L.paam_wcrt_bytes.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), ctypes.POINTER(S)]
         L.paam_wcrt_batch.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P, S, P]
+        L.paam_search_bytes.argtypes = [P, ctypes.POINTER(paam_search_opts), ctypes.POINTER(S)]
+        L.paam_priority_search.argtypes = [P, ctypes.POINTER(paam_search_opts), P, P, P, P, S, P]
         L.paam_last_error.argtypes = []
         L.paam_last_error.restype = ctypes.c_char_p
         L.paam_version.argtypes = []
         L.paam_version.restype = ctypes.c_char_p
         for f in ("paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_info",
-                  "paam_wcrt_bytes", "paam_wcrt_batch"):
+                  "paam_wcrt_bytes", "paam_wcrt_batch", "paam_search_bytes",
+                  "paam_priority_search"):
             getattr(L, f).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -192,3 +202,50 @@ def wcrt(cs: Chainset, stream=None, **kw) -> dict:
     if out.chain_R is not None:
         res["chain_R"] = out.chain_R.cpu().numpy()[:cs.n_chains]
     return res
+
+
+def search_opts(n_cand, seed, guided=False, top_k=1, fallback=True, scores=None,
+                **wcrt_kw) -> paam_search_opts:
+    return paam_search_opts(n_cand=n_cand, guided=1 if guided else 0, top_k=top_k,
+                            fallback=1 if fallback else 0, seed=seed & (2**64 - 1),
+                            d_scores=None if scores is None else scores.data_ptr(),
+                            wcrt=wcrt_opts(full=False, **wcrt_kw))
+
+
+def paam_search_bytes(cs: Chainset, opts: paam_search_opts) -> int:
+    n = ctypes.c_size_t(0)
+    check(lib().paam_search_bytes(cs.handle, ctypes.byref(opts), ctypes.byref(n)),
+          "paam_search_bytes")
+    return int(n.value)
+
+
+class SearchOut:
+    def __init__(self, cs: Chainset, with_prio: bool = True):
+        import torch
+        d = cs.device
+        self.found = torch.empty(cs.n_sets, dtype=torch.int32, device=d)
+        self.n_exact = torch.empty(cs.n_sets, dtype=torch.int32, device=d)
+        self.found_prio = (torch.zeros(max(cs.n_chains, 1), dtype=torch.int32, device=d)
+                           if with_prio else None)
+
+
+def paam_priority_search(cs: Chainset, opts: paam_search_opts, out: SearchOut, ws,
+                         stream=None) -> None:
+    check(lib().paam_priority_search(cs.handle, ctypes.byref(opts), out.found.data_ptr(),
+                                     out.n_exact.data_ptr(), _dev_ptr(out.found_prio),
+                                     ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+          "paam_priority_search")
+
+
+def search(cs: Chainset, n_cand: int, seed: int, stream=None, scores=None, guided=False,
+           top_k=1, fallback=True, **wcrt_kw) -> dict:
+    """One priority-order search over an uploaded batch; host numpy results."""
+    import torch
+    o = search_opts(n_cand, seed, guided=guided, top_k=top_k, fallback=fallback, scores=scores,
+                    **wcrt_kw)
+    out = SearchOut(cs)
+    ws = workspace(paam_search_bytes(cs, o), cs.device)
+    paam_priority_search(cs, o, out, ws, stream)
+    torch.cuda.synchronize()
+    return {"found": out.found.cpu().numpy(), "n_exact": out.n_exact.cpu().numpy(),
+            "found_prio": out.found_prio.cpu().numpy()[:cs.n_chains]}

@@ -11,6 +11,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "paam_internal.h"
@@ -65,13 +66,13 @@ struct Plan {
   int64_t n_sets = 0, n_chains = 0, n_cbs = 0, n_segs = 0, n_runs = 0, n_exec = 0, n_accel = 0;
   std::vector<int64_t> set_cb_off, set_seg_off, set_run_off;
   std::vector<int16_t> run_chain, run_exec;
-  std::vector<int32_t> run_cb_lo, run_cb_hi, chain_nrun, exec_runs, er_off, er_cnt;
-  std::vector<int16_t> rank0, seg_chain, exec_seq;
+  std::vector<int32_t> run_cb_lo, run_cb_hi, chain_nrun, seg_order;
+  std::vector<int16_t> rank0, seg_chain;
   std::vector<uint32_t> hpx_mask;
   std::vector<double> Kd, rcp;
   std::vector<int32_t> buckets;
   std::vector<int64_t> work_order;
-  int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0, max_runs_exec = 0;
+  int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0;
 };
 
 #define REQ(cond, ...)                                   \
@@ -82,6 +83,155 @@ struct Plan {
   do {                                                   \
     if (!(cond)) return fail(PAAM_E_RANGE, __VA_ARGS__); \
   } while (0)
+
+// Runs f(lo, hi) over [0, n) on a few threads; returns the status of the
+// lowest failing range (and keeps its message), or PAAM_OK.
+template <class F>
+paam_status parallel_ranges(int64_t n, F f) {
+  int nt = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+  if (n < 4096) nt = 1;
+  std::vector<paam_status> st(nt, PAAM_OK);
+  std::vector<std::string> msg(nt);
+  auto body = [&](int t) {
+    const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+    st[t] = f(lo, hi);
+    if (st[t] != PAAM_OK) msg[t] = g_err;
+  };
+  if (nt == 1) {
+    body(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(body, t);
+    for (auto &x : th) x.join();
+  }
+  for (int t = 0; t < nt; ++t)
+    if (st[t] != PAAM_OK) {
+      g_err = msg[t];
+      return st[t];
+    }
+  return PAAM_OK;
+}
+
+// Validates one set and returns its sub-chain count in *nrun.
+paam_status check_set(const paam_chainset_host *h, int64_t s, int *nrun, double *cost) {
+  using paam::kTimeLimit;
+  const int64_t c0 = h->set_chain_off[s];
+  const int C = (int)(h->set_chain_off[s + 1] - c0);
+  const int64_t x0 = h->set_exec_off[s];
+  const int X = (int)(h->set_exec_off[s + 1] - x0);
+  const int NA = (int)(h->set_accel_off[s + 1] - h->set_accel_off[s]);
+  for (int e = 0; e < X; ++e)
+    for (int f = 0; f < e; ++f)
+      REQ(!(h->exec_core[x0 + e] == h->exec_core[x0 + f] &&
+            h->exec_prio[x0 + e] == h->exec_prio[x0 + f]),
+          "set %lld: executors %d and %d share core and process priority", (long long)s, f, e);
+  std::vector<int32_t> pr(C);
+  for (int c = 0; c < C; ++c) pr[c] = h->prio[c0 + c];
+  std::sort(pr.begin(), pr.end());
+  for (int c = 1; c < C; ++c)
+    REQ(pr[c] != pr[c - 1], "set %lld: duplicate chain priority", (long long)s);
+  int runs = 0;
+  for (int c = 0; c < C; ++c) {
+    const int64_t T = h->T[c0 + c], D = h->D[c0 + c];
+    REQ(T > 0 && D > 0 && D <= T, "chain %lld: need 0 < D <= T (T=%lld D=%lld)",
+        (long long)(c0 + c), (long long)T, (long long)D);
+    RNG(T < kTimeLimit, "chain %lld: period >= 2^36 ns", (long long)(c0 + c));
+    int prev_e = -1;
+    for (int64_t j = h->chain_cb_off[c0 + c]; j < h->chain_cb_off[c0 + c + 1]; ++j) {
+      const int e = h->exec[j];
+      REQ(e >= 0 && e < X, "callback %lld: executor %d out of range", (long long)j, e);
+      REQ(h->E[j] >= 0, "callback %lld: negative E", (long long)j);
+      RNG(h->E[j] < kTimeLimit, "callback %lld: E >= 2^36 ns", (long long)j);
+      for (int64_t g = h->cb_seg_off[j]; g < h->cb_seg_off[j + 1]; ++g) {
+        REQ(h->A[g] >= 0, "segment %lld: negative A", (long long)g);
+        RNG(h->A[g] < kTimeLimit, "segment %lld: A >= 2^36 ns", (long long)g);
+        REQ(h->accel[g] >= 0 && h->accel[g] < NA, "segment %lld: accelerator out of range",
+            (long long)g);
+      }
+      if (e != prev_e) ++runs;
+      prev_e = e;
+    }
+  }
+  RNG(runs <= paam::kMaxRuns, "set %lld: %d sub-chains (max %d)", (long long)s, runs,
+      paam::kMaxRuns);
+  RNG(h->eps_hop[s] >= 0 && h->eps_hop[s] < kTimeLimit, "set %lld: hop cost outside [0, 2^36)",
+      (long long)s);
+  const int64_t cb0 = h->chain_cb_off[c0], cb1 = h->chain_cb_off[c0 + C];
+  const int64_t nseg = h->cb_seg_off[cb1] - h->cb_seg_off[cb0];
+  RNG(nseg <= (int64_t)1 << 30 && cb1 - cb0 <= (int64_t)1 << 30, "set %lld too large",
+      (long long)s);
+  *nrun = runs;
+  *cost = (double)runs * (double)(C + 4) + (double)nseg * (double)C;
+  return PAAM_OK;
+}
+
+// Fills the derived arrays of one set (after validation).
+void fill_set(const paam_chainset_host *h, int64_t s, Plan &P) {
+  const int64_t c0 = h->set_chain_off[s];
+  const int C = (int)(h->set_chain_off[s + 1] - c0);
+  const int64_t x0 = h->set_exec_off[s];
+  const int X = (int)(h->set_exec_off[s + 1] - x0);
+  const int64_t cb0 = h->chain_cb_off[c0], cb1 = h->chain_cb_off[c0 + C];
+  const int64_t g0 = h->cb_seg_off[cb0], g1 = h->cb_seg_off[cb1];
+  P.set_cb_off[s] = cb0;
+  P.set_seg_off[s] = g0;
+  for (int e = 0; e < X; ++e) {
+    uint32_t m = 0;
+    for (int f = 0; f < X; ++f)
+      if (f != e && h->exec_core[x0 + e] == h->exec_core[x0 + f] &&
+          h->exec_prio[x0 + f] > h->exec_prio[x0 + e])
+        m |= 1u << f;
+    P.hpx_mask[x0 + e] = m;
+  }
+  std::vector<int> order(C);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return h->prio[c0 + a] > h->prio[c0 + b]; });
+  for (int r = 0; r < C; ++r) {
+    const int c = order[r];
+    P.rank0[c0 + c] = (int16_t)r;
+  }
+  // sub-chains in chain order, then sorted by (hpp above, rank, position)
+  struct Run {
+    int16_t chain, exec;
+    int32_t lo, hi;
+  };
+  std::vector<Run> runs;
+  for (int c = 0; c < C; ++c) {
+    int prev_e = -1;
+    for (int64_t j = h->chain_cb_off[c0 + c]; j < h->chain_cb_off[c0 + c + 1]; ++j) {
+      const int e = h->exec[j];
+      const int jl = (int)(j - cb0);
+      if (e != prev_e) {
+        runs.push_back(Run{(int16_t)c, (int16_t)e, jl, jl + 1});
+        prev_e = e;
+      } else {
+        runs.back().hi = jl + 1;
+      }
+    }
+    for (int64_t j = h->chain_cb_off[c0 + c]; j < h->chain_cb_off[c0 + c + 1]; ++j)
+      for (int64_t g = h->cb_seg_off[j]; g < h->cb_seg_off[j + 1]; ++g) P.seg_chain[g] = (int16_t)c;
+  }
+  for (const Run &r : runs) P.chain_nrun[c0 + r.chain]++;
+  std::stable_sort(runs.begin(), runs.end(), [&](const Run &a, const Run &b) {
+    const bool pa = P.hpx_mask[x0 + a.exec] != 0, pb = P.hpx_mask[x0 + b.exec] != 0;
+    if (pa != pb) return pa < pb;
+    return P.rank0[c0 + a.chain] < P.rank0[c0 + b.chain];
+  });
+  const int64_t r0 = P.set_run_off[s];
+  for (size_t i = 0; i < runs.size(); ++i) {
+    P.run_chain[r0 + i] = runs[i].chain;
+    P.run_exec[r0 + i] = runs[i].exec;
+    P.run_cb_lo[r0 + i] = runs[i].lo;
+    P.run_cb_hi[r0 + i] = runs[i].hi;
+  }
+  std::vector<int32_t> so((size_t)(g1 - g0));
+  std::iota(so.begin(), so.end(), 0);
+  std::stable_sort(so.begin(), so.end(), [&](int a, int b) {
+    return P.rank0[c0 + P.seg_chain[g0 + a]] < P.rank0[c0 + P.seg_chain[g0 + b]];
+  });
+  std::copy(so.begin(), so.end(), P.seg_order.begin() + g0);
+}
 
 paam_status make_plan(const paam_chainset_host *h, Plan &P) {
   using paam::kTimeLimit;
@@ -122,29 +272,6 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
   const int64_t NG = h->cb_seg_off[NJ];
   P.n_segs = NG;
   REQ(NG == 0 || (h->A && h->accel), "segments present but A/accel null");
-
-  // executors, accelerators
-  P.hpx_mask.assign(NX, 0u);
-  P.exec_seq.assign(NX, 0);
-  for (int64_t s = 0; s < S; ++s) {
-    const int64_t x0 = h->set_exec_off[s];
-    const int X = (int)(h->set_exec_off[s + 1] - x0);
-    for (int e = 0; e < X; ++e)
-      for (int f = 0; f < X; ++f) {
-        if (e == f || h->exec_core[x0 + e] != h->exec_core[x0 + f]) continue;
-        REQ(h->exec_prio[x0 + e] != h->exec_prio[x0 + f],
-            "set %lld: executors %d and %d share core and process priority", (long long)s, e, f);
-        if (h->exec_prio[x0 + f] > h->exec_prio[x0 + e]) P.hpx_mask[x0 + e] |= 1u << f;
-      }
-    std::vector<int> seq(X);
-    std::iota(seq.begin(), seq.end(), 0);
-    std::stable_sort(seq.begin(), seq.end(), [&](int a, int b) {
-      if (h->exec_core[x0 + a] != h->exec_core[x0 + b])
-        return h->exec_core[x0 + a] < h->exec_core[x0 + b];
-      return h->exec_prio[x0 + a] > h->exec_prio[x0 + b];
-    });
-    for (int i = 0; i < X; ++i) P.exec_seq[x0 + i] = (int16_t)seq[i];
-  }
   P.buckets.resize(NAc);
   for (int64_t a = 0; a < NAc; ++a) {
     REQ(h->accel_buckets[a] >= 1, "accelerator %lld: buckets < 1", (long long)a);
@@ -155,110 +282,55 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     P.buckets[a] = h->accel_buckets[a];
   }
 
-  // chains
-  P.Kd.resize(NC);
-  P.rcp.resize(NC);
-  P.rank0.resize(NC);
-  P.chain_nrun.assign(NC, 0);
-  for (int64_t c = 0; c < NC; ++c) {
-    const int64_t T = h->T[c], D = h->D[c];
-    REQ(T > 0 && D > 0 && D <= T, "chain %lld: need 0 < D <= T (T=%lld D=%lld)", (long long)c,
-        (long long)T, (long long)D);
-    RNG(T < kTimeLimit, "chain %lld: period >= 2^36 ns", (long long)c);
-    P.Kd[c] = (double)(2 * T - 1);
-    P.rcp[c] = rcp_up(T);
-  }
-
-  // sets: ranks, sub-chains, grouping by executor, segments' chains
+  // pass 1: validate every set, count its sub-chains
+  std::vector<int> nrun(S);
+  std::vector<double> cost(S);
+  paam_status st = parallel_ranges(S, [&](int64_t lo, int64_t hi) -> paam_status {
+    for (int64_t s = lo; s < hi; ++s) {
+      paam_status r = check_set(h, s, &nrun[s], &cost[s]);
+      if (r != PAAM_OK) return r;
+    }
+    return PAAM_OK;
+  });
+  if (st != PAAM_OK) return st;
   P.set_cb_off.resize(S + 1);
   P.set_seg_off.resize(S + 1);
-  P.set_run_off.resize(S + 1);
-  P.seg_chain.resize(NG);
-  P.er_off.assign(NX, 0);
-  P.er_cnt.assign(NX, 0);
-  std::vector<double> cost(S);
+  P.set_run_off.assign(S + 1, 0);
   for (int64_t s = 0; s < S; ++s) {
+    P.set_run_off[s + 1] = P.set_run_off[s] + nrun[s];
     const int64_t c0 = h->set_chain_off[s];
     const int C = (int)(h->set_chain_off[s + 1] - c0);
-    const int64_t x0 = h->set_exec_off[s];
-    const int X = (int)(h->set_exec_off[s + 1] - x0);
-    const int NA = (int)(h->set_accel_off[s + 1] - h->set_accel_off[s]);
     const int64_t cb0 = h->chain_cb_off[c0], cb1 = h->chain_cb_off[c0 + C];
-    const int64_t g0 = h->cb_seg_off[cb0], g1 = h->cb_seg_off[cb1];
-    P.set_cb_off[s] = cb0;
-    P.set_seg_off[s] = g0;
-    P.set_run_off[s] = (int64_t)P.run_chain.size();
-    RNG(g1 - g0 <= (int64_t)1 << 30 && cb1 - cb0 <= (int64_t)1 << 30, "set %lld too large",
-        (long long)s);
-    std::vector<int> order(C);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return h->prio[c0 + a] > h->prio[c0 + b]; });
-    for (int r = 0; r < C; ++r) {
-      if (r > 0)
-        REQ(h->prio[c0 + order[r]] != h->prio[c0 + order[r - 1]],
-            "set %lld: duplicate chain priority", (long long)s);
-      P.rank0[c0 + order[r]] = (int16_t)r;
-    }
-    const size_t runs_begin = P.run_chain.size();
-    for (int c = 0; c < C; ++c) {
-      int prev_e = -1;
-      for (int64_t j = h->chain_cb_off[c0 + c]; j < h->chain_cb_off[c0 + c + 1]; ++j) {
-        const int e = h->exec[j];
-        REQ(e >= 0 && e < X, "callback %lld: executor %d out of range", (long long)j, e);
-        REQ(h->E[j] >= 0, "callback %lld: negative E", (long long)j);
-        RNG(h->E[j] < kTimeLimit, "callback %lld: E >= 2^36 ns", (long long)j);
-        for (int64_t g = h->cb_seg_off[j]; g < h->cb_seg_off[j + 1]; ++g) {
-          REQ(h->A[g] >= 0, "segment %lld: negative A", (long long)g);
-          RNG(h->A[g] < kTimeLimit, "segment %lld: A >= 2^36 ns", (long long)g);
-          REQ(h->accel[g] >= 0 && h->accel[g] < NA, "segment %lld: accelerator out of range",
-              (long long)g);
-          P.seg_chain[g] = (int16_t)c;
-        }
-        const int jl = (int)(j - cb0);
-        if (e != prev_e) {
-          P.run_chain.push_back((int16_t)c);
-          P.run_exec.push_back((int16_t)e);
-          P.run_cb_lo.push_back(jl);
-          P.run_cb_hi.push_back(jl + 1);
-          P.chain_nrun[c0 + c]++;
-          prev_e = e;
-        } else {
-          P.run_cb_hi.back() = jl + 1;
-        }
-      }
-    }
-    const int nrun = (int)(P.run_chain.size() - runs_begin);
-    RNG(nrun <= paam::kMaxRuns, "set %lld: %d sub-chains (max %d)", (long long)s, nrun,
-        paam::kMaxRuns);
-    // group sub-chains by executor
-    std::vector<int> cnt(X, 0);
-    for (int r = 0; r < nrun; ++r) cnt[P.run_exec[runs_begin + r]]++;
-    int off = 0, mre = 0;
-    for (int e = 0; e < X; ++e) {
-      P.er_off[x0 + e] = off;
-      P.er_cnt[x0 + e] = cnt[e];
-      off += cnt[e];
-      mre = std::max(mre, cnt[e]);
-    }
-    std::vector<int> pos(X);
-    for (int e = 0; e < X; ++e) pos[e] = P.er_off[x0 + e];
-    P.exec_runs.resize(runs_begin + nrun);
-    for (int r = 0; r < nrun; ++r) P.exec_runs[runs_begin + pos[P.run_exec[runs_begin + r]]++] = r;
     P.max_C = std::max(P.max_C, C);
-    P.max_X = std::max(P.max_X, X);
-    P.max_NA = std::max(P.max_NA, NA);
-    P.max_runs = std::max(P.max_runs, nrun);
-    P.max_segs = std::max(P.max_segs, (int32_t)(g1 - g0));
-    P.max_runs_exec = std::max(P.max_runs_exec, mre);
-    cost[s] = (double)nrun * (double)(C + 4) + (double)(g1 - g0) * (double)C;
+    P.max_X = std::max(P.max_X, (int32_t)(h->set_exec_off[s + 1] - h->set_exec_off[s]));
+    P.max_NA = std::max(P.max_NA, (int32_t)(h->set_accel_off[s + 1] - h->set_accel_off[s]));
+    P.max_runs = std::max(P.max_runs, nrun[s]);
+    P.max_segs = std::max(P.max_segs, (int32_t)(h->cb_seg_off[cb1] - h->cb_seg_off[cb0]));
   }
-  for (int64_t s = 0; s < S; ++s) RNG(h->eps_hop[s] >= 0 && h->eps_hop[s] < kTimeLimit,
-                                      "set %lld: hop cost outside [0, 2^36)", (long long)s);
+  P.n_runs = P.set_run_off[S];
   P.set_cb_off[S] = NJ;
   P.set_seg_off[S] = NG;
-  P.set_run_off[S] = (int64_t)P.run_chain.size();
-  P.n_runs = (int64_t)P.run_chain.size();
+
+  // pass 2: derived arrays
+  P.Kd.resize(NC);
+  P.rcp.resize(NC);
+  for (int64_t c = 0; c < NC; ++c) {
+    P.Kd[c] = (double)(2 * h->T[c] - 1);
+    P.rcp[c] = rcp_up(h->T[c]);
+  }
+  P.rank0.resize(NC);
+  P.chain_nrun.assign(NC, 0);
+  P.seg_chain.resize(NG);
+  P.seg_order.resize(NG);
+  P.hpx_mask.assign(NX, 0u);
+  P.run_chain.resize(P.n_runs);
+  P.run_exec.resize(P.n_runs);
+  P.run_cb_lo.resize(P.n_runs);
+  P.run_cb_hi.resize(P.n_runs);
+  parallel_ranges(S, [&](int64_t lo, int64_t hi) -> paam_status {
+    for (int64_t s = lo; s < hi; ++s) fill_set(h, s, P);
+    return PAAM_OK;
+  });
   P.work_order.resize(S);
   std::iota(P.work_order.begin(), P.work_order.end(), 0);
   std::stable_sort(P.work_order.begin(), P.work_order.end(),
@@ -279,9 +351,9 @@ struct Arena {
 
 struct Offsets {
   size_t set_chain_off, set_cb_off, set_seg_off, set_run_off, set_exec_off, set_accel_off, eps_hop,
-      work_order, T, D, Kd, rcp, rank0, chain_nrun, spin, E, cb_seg_off, A, seg_accel, seg_chain,
-      run_chain, run_exec, run_cb_lo, run_cb_hi, exec_runs, er_off, er_cnt, hpx_mask, exec_seq,
-      buckets, aeps, akappa, total;
+      work_order, T, D, Kd, rcp, rank0, chain_nrun, spin, E, cb_seg_off, A, seg_accel,
+      seg_chain, seg_order, run_chain, run_exec, run_cb_lo, run_cb_hi, hpx_mask, buckets, aeps,
+      akappa, total;
 };
 
 Offsets layout(const Plan &P) {
@@ -308,15 +380,12 @@ Offsets layout(const Plan &P) {
   o.A = a.take<int64_t>(P.n_segs);
   o.seg_accel = a.take<int16_t>(P.n_segs);
   o.seg_chain = a.take<int16_t>(P.n_segs);
+  o.seg_order = a.take<int32_t>(P.n_segs);
   o.run_chain = a.take<int16_t>(P.n_runs);
   o.run_exec = a.take<int16_t>(P.n_runs);
   o.run_cb_lo = a.take<int32_t>(P.n_runs);
   o.run_cb_hi = a.take<int32_t>(P.n_runs);
-  o.exec_runs = a.take<int32_t>(P.n_runs);
-  o.er_off = a.take<int32_t>(P.n_exec);
-  o.er_cnt = a.take<int32_t>(P.n_exec);
   o.hpx_mask = a.take<uint32_t>(P.n_exec);
-  o.exec_seq = a.take<int16_t>(P.n_exec);
   o.buckets = a.take<int32_t>(P.n_accel);
   o.aeps = a.take<int64_t>(P.n_accel);
   o.akappa = a.take<int64_t>(P.n_accel);
@@ -391,15 +460,12 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   put(buf, o.A, h->A, P.n_segs);
   put(buf, o.seg_accel, h->accel, P.n_segs);
   put(buf, o.seg_chain, P.seg_chain.data(), P.n_segs);
+  put(buf, o.seg_order, P.seg_order.data(), P.n_segs);
   put(buf, o.run_chain, P.run_chain.data(), P.n_runs);
   put(buf, o.run_exec, P.run_exec.data(), P.n_runs);
   put(buf, o.run_cb_lo, P.run_cb_lo.data(), P.n_runs);
   put(buf, o.run_cb_hi, P.run_cb_hi.data(), P.n_runs);
-  put(buf, o.exec_runs, P.exec_runs.data(), P.n_runs);
-  put(buf, o.er_off, P.er_off.data(), P.n_exec);
-  put(buf, o.er_cnt, P.er_cnt.data(), P.n_exec);
   put(buf, o.hpx_mask, P.hpx_mask.data(), P.n_exec);
-  put(buf, o.exec_seq, P.exec_seq.data(), P.n_exec);
   put(buf, o.buckets, P.buckets.data(), P.n_accel);
   put(buf, o.aeps, h->accel_eps, P.n_accel);
   put(buf, o.akappa, h->accel_kappa, P.n_accel);
@@ -440,15 +506,12 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   BIND(A, int64_t);
   BIND(seg_accel, int16_t);
   BIND(seg_chain, int16_t);
+  BIND(seg_order, int32_t);
   BIND(run_chain, int16_t);
   BIND(run_exec, int16_t);
   BIND(run_cb_lo, int32_t);
   BIND(run_cb_hi, int32_t);
-  BIND(exec_runs, int32_t);
-  BIND(er_off, int32_t);
-  BIND(er_cnt, int32_t);
   BIND(hpx_mask, uint32_t);
-  BIND(exec_seq, int16_t);
   BIND(buckets, int32_t);
   BIND(aeps, int64_t);
   BIND(akappa, int64_t);
@@ -458,7 +521,6 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   b.max_NA = P.max_NA;
   b.max_runs = std::max(P.max_runs, 1);
   b.max_segs = std::max(P.max_segs, 1);
-  b.max_runs_exec = P.max_runs_exec;
   cs->arena_bytes = o.total;
   cs->n_exec = P.n_exec;
   cs->n_accel = P.n_accel;
@@ -541,6 +603,59 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
     return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)", L.lds_bytes);
   int e = paam::launch_wcrt(L, stream);
   if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
+  return PAAM_OK;
+}
+
+static paam_status check_search(const paam_chainset *cs, const paam_search_opts *o) {
+  if (!cs || !o) return fail(PAAM_E_INVAL, "null argument");
+  paam_status st = check_opts(&o->wcrt);
+  if (st != PAAM_OK) return st;
+  if (o->n_cand < 1 || o->n_cand > 65536) return fail(PAAM_E_INVAL, "n_cand must be 1..65536");
+  if (o->guided != 0 && o->guided != 1) return fail(PAAM_E_INVAL, "guided must be 0 or 1");
+  if (o->guided) {
+    if (o->top_k < 1 || o->top_k > o->n_cand) return fail(PAAM_E_INVAL, "top_k must be 1..n_cand");
+    if (!o->d_scores) return fail(PAAM_E_INVAL, "guided search needs d_scores");
+    if (o->top_k > 1024) return fail(PAAM_E_INVAL, "top_k must be <= 1024");
+  }
+  return PAAM_OK;
+}
+
+paam_status paam_search_bytes(const paam_chainset *cs, const paam_search_opts *o, size_t *ws_bytes) {
+  if (!ws_bytes) return fail(PAAM_E_INVAL, "null argument");
+  paam_status st = check_search(cs, o);
+  if (st != PAAM_OK) return st;
+  *ws_bytes = 256 + (size_t)grid_for(cs, &o->wcrt) * paam::wave_search_bytes(cs->dev);
+  return PAAM_OK;
+}
+
+paam_status paam_priority_search(const paam_chainset *cs, const paam_search_opts *o,
+                                 int32_t *found, int32_t *n_exact, int32_t *found_prio, void *d_ws,
+                                 size_t ws_bytes, paam_stream stream) {
+  paam_status st = check_search(cs, o);
+  if (st != PAAM_OK) return st;
+  if (!found || !n_exact) return fail(PAAM_E_INVAL, "found and n_exact must not be null");
+  size_t need = 0;
+  paam_search_bytes(cs, o, &need);
+  if (!d_ws || ws_bytes < need)
+    return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
+    return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
+  paam::SearchLaunch L;
+  L.b = cs->dev;
+  L.o = *o;
+  L.found = found;
+  L.n_exact = n_exact;
+  L.found_prio = found_prio;
+  L.counter = static_cast<unsigned long long *>(d_ws);
+  L.scratch = static_cast<unsigned char *>(d_ws) + 256;
+  L.scratch_stride = paam::wave_search_bytes(cs->dev);
+  L.analysis_stride = paam::wave_scratch_bytes(cs->dev);
+  L.lds_bytes = paam::wave_lds_bytes(cs->dev);
+  L.grid = grid_for(cs, &o->wcrt);
+  if (L.lds_bytes > 160 * 1024)
+    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)", L.lds_bytes);
+  int e = paam::launch_search(L, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "search launch");
   return PAAM_OK;
 }
 

@@ -15,6 +15,10 @@
 
 namespace paam {
 
+struct double2_t {
+  double x, y;
+};
+
 constexpr int kWave = 64;
 constexpr int kMaxExec = 32;     // executors per set (hpp masks are 32-bit)
 constexpr int kMaxAccel = 8;     // accelerators per set (accelerator masks are 8-bit)
@@ -45,20 +49,19 @@ struct DevBatch {
   const int64_t *A;            // [n_segs]
   const int16_t *seg_accel;    // [n_segs]
   const int16_t *seg_chain;    // [n_segs]
-  // sub-chains, set-local ids in chain order
-  const int16_t *run_chain;    // [n_runs]
+  const int32_t *seg_order;    // [n_segs] per set: set-local segment ids by rank of their chain
+  // sub-chains per set, ordered by (executor has hpp executors above it,
+  // rank of the chain under the uploaded priorities, position in the chain)
+  const int16_t *run_chain;    // [n_runs] set-local chain
   const int16_t *run_exec;     // [n_runs]
   const int32_t *run_cb_lo, *run_cb_hi;  // [n_runs] set-local callback range
-  const int32_t *exec_runs;    // [n_runs] per set: sub-chain ids grouped by executor
   // executors
-  const int32_t *er_off, *er_cnt;  // [n_exec] position/count of the executor's group
   const uint32_t *hpx_mask;        // [n_exec] executors of the same core with higher process priority
-  const int16_t *exec_seq;         // [n_exec] per set: executors in solving order
   // accelerators
   const int32_t *buckets;          // [n_accels]
   const int64_t *aeps, *akappa;    // [n_accels]
   // per-set maxima over the batch
-  int32_t max_C, max_X, max_NA, max_runs, max_segs, max_runs_exec;
+  int32_t max_C, max_X, max_NA, max_runs, max_segs;
 };
 
 }  // namespace paam
@@ -85,11 +88,27 @@ struct WcrtLaunch {
   int grid;
 };
 
+struct SearchLaunch {
+  DevBatch b;
+  paam_search_opts o;
+  int32_t *found;               // [n_sets]
+  int32_t *n_exact;             // [n_sets]
+  int32_t *found_prio;          // [n_chains] or null
+  unsigned long long *counter;
+  unsigned char *scratch;
+  size_t scratch_stride;        // bytes per wave: analysis scratch + search slot
+  size_t analysis_stride;       // offset of the search slot in a wave's scratch
+  size_t lds_bytes;
+  int grid;
+};
+
 // Scratch and LDS sizes for one wave analysing one set at a time.
 size_t wave_scratch_bytes(const DevBatch &b);
 size_t wave_lds_bytes(const DevBatch &b);
+size_t wave_search_bytes(const DevBatch &b);
 
 // Launches (defined in paam_kernels.hip); return a hipError_t as int.
 int launch_wcrt(const WcrtLaunch &L, void *stream);
+int launch_search(const SearchLaunch &L, void *stream);
 
 }  // namespace paam

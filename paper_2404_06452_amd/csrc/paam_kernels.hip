@@ -12,13 +12,14 @@
 // all full-rate on CDNA4, instead of an integer division.
 //
 // Schedule.  One wavefront per chain set, pulled from a work queue in
-// decreasing estimated cost.  Lanes run over segments (Lemma 2), then over the
-// sub-chains of one executor at a time (Theorem 1).  Executors of a core are
-// solved from the highest process priority down, so the hpp weights of
-// Theorem 1 are final when an executor starts; inside an executor all
-// sub-chains iterate together (Jacobi) until no value changes.  Every
-// iteration starts below the least fixed point and is monotone, so the
-// result is the same least fixed point a sequential evaluation reaches.
+// decreasing estimated cost.  Lanes run over segments (Lemma 2), then over
+// sub-chains (Theorem 1).  All sub-chains of a set iterate together: every
+// sweep rebuilds the per-executor interference weights (hp and hpp terms of
+// Eq. 6) from the current H* values and re-evaluates, packed into full
+// 64-lane chunks, only the sub-chains that have not converged or whose
+// weights changed.  Each iterate starts below the least fixed point and the
+// system is monotone, so this chaotic iteration ends at the same least fixed
+// point a sequential evaluation in dependency order reaches.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -42,10 +43,6 @@ __device__ __forceinline__ void lds_max(double *p, double v) {
 
 __device__ __forceinline__ int wave_any(bool p) { return __any(p); }
 
-__device__ __forceinline__ int wave_min_int(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
-}
 __device__ __forceinline__ int wave_max_int(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
   return v;
@@ -60,40 +57,42 @@ __device__ __forceinline__ bool ratio_gt(double Ra, int64_t Da, double Rb, int64
   return l > r;
 }
 
+// LDS of one wave.  Tables by rank (0 = highest priority) with row stride C.
 struct Lds {
-  double *K, *rc, *cap, *Dd, *partial, *W, *Wn, *P, *Hs;  // [C] by rank
-  double *Ahat, *amax, *Bacc;                             // [NA][C]
-  double *Ece, *epsce, *SB, *Hfin;                        // [X][C]
-  int32_t *perm, *rank, *nrun, *spinf;                    // [C]
-  int32_t *level, *uses;                                  // [NA][C]
-  int32_t *misc;                                          // [16]
+  double2 *KR;                       // [C] (2T-1, 1/T up) of the chain at a rank
+  double *cap, *Dd, *partial;        // [C]
+  double *Ahat, *amax, *Bacc;        // [NA][C]
+  double *Ece, *epsce, *Hs;          // [X][C] per chain and executor: E sum, eps sum, H* sum
+  double *WP, *Pt;                   // [X][C] hp+hpp weight (rank above), hpp weight (below)
+  double *SB;                        // [X][C] blocking candidates (aliases Pt before Theorem 1)
+  int32_t *perm, *rank, *nrun, *spinf;  // [C]
+  int32_t *level, *uses;             // [NA][C]
+  int32_t *wmin, *pmax;              // [X] lowest rank whose WP changed, highest whose Pt changed
+  int32_t *misc;                     // [16]
 };
 
 struct Scratch {
-  double *segAs, *segH;                          // [max_segs]
-  double *r, *hs, *cst, *L2, *A0, *eps;          // [max_runs]
-  int32_t *info0, *info1;                        // [max_runs]
+  double *segAs, *segH;                    // [max_segs]
+  double *r, *hs, *cst, *L2, *A0, *eps;    // [max_runs]
+  int32_t *info0, *info1, *alist;          // [max_runs]
 };
 
 __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   Lds l;
   double *d = reinterpret_cast<double *>(base);
-  l.K = d; d += Cm;
-  l.rc = d; d += Cm;
+  l.KR = reinterpret_cast<double2 *>(d); d += 2 * Cm;
   l.cap = d; d += Cm;
   l.Dd = d; d += Cm;
   l.partial = d; d += Cm;
-  l.W = d; d += Cm;
-  l.Wn = d; d += Cm;
-  l.P = d; d += Cm;
-  l.Hs = d; d += Cm;
   l.Ahat = d; d += NAm * Cm;
   l.amax = d; d += NAm * Cm;
   l.Bacc = d; d += NAm * Cm;
   l.Ece = d; d += Xm * Cm;
   l.epsce = d; d += Xm * Cm;
-  l.SB = d; d += Xm * Cm;
-  l.Hfin = d; d += Xm * Cm;
+  l.Hs = d; d += Xm * Cm;
+  l.WP = d; d += Xm * Cm;
+  l.Pt = d; d += Xm * Cm;
+  l.SB = l.Pt;
   int32_t *i = reinterpret_cast<int32_t *>(d);
   l.perm = i; i += Cm;
   l.rank = i; i += Cm;
@@ -101,6 +100,8 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   l.spinf = i; i += Cm;
   l.level = i; i += NAm * Cm;
   l.uses = i; i += NAm * Cm;
+  l.wmin = i; i += Xm;
+  l.pmax = i; i += Xm;
   l.misc = i;
   return l;
 }
@@ -118,7 +119,8 @@ __device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs
   s.eps = d; d += max_runs;
   int32_t *i = reinterpret_cast<int32_t *>(d);
   s.info0 = i; i += max_runs;
-  s.info1 = i;
+  s.info1 = i; i += max_runs;
+  s.alist = i;
   return s;
 }
 
@@ -127,13 +129,12 @@ __device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs
 // reports set_sched = -1.
 constexpr int kMaxIter = 1 << 20;
 
-constexpr int kNeedL3 = 1 << 8;
-constexpr int kConv = 1 << 9;
-constexpr int kHasSeg = 1 << 10;
+// info1 bits of a sub-chain: accelerator mask in bits 0-7
+constexpr int kNeedL3 = 1 << 8;  // H* follows Lemma 3 at the current window
+constexpr int kConv = 1 << 9;    // last evaluation changed nothing
 
-// Analyses set `set` under the priority order perm (chain ids, highest
-// first) if given, else under the uploaded priorities.  Writes the outputs
-// of that set.  Called by all 64 lanes of a wave.
+// Analyses one set under the uploaded priorities and writes its outputs.
+// Called by all 64 lanes of a wave.
 __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t set, Lds &L,
                             Scratch &S, int8_t *set_sched, int32_t *set_worst,
                             int64_t *set_worst_R, int64_t *chain_R) {
@@ -158,8 +159,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     const int rho = b.rank0[c0 + c];
     L.perm[rho] = c;
     L.rank[c] = rho;
-    L.K[rho] = b.Kd[c0 + c];
-    L.rc[rho] = b.rcp[c0 + c];
+    L.KR[rho] = make_double2(b.Kd[c0 + c], b.rcp[c0 + c]);
     const int64_t D = b.D[c0 + c];
     L.Dd[rho] = (double)D;
     L.cap[rho] = (double)D * (double)o.cap_mult;
@@ -175,8 +175,9 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   for (int i = lane; i < X * C; i += kWave) {
     L.Ece[i] = 0.0;
     L.epsce[i] = 0.0;
+    L.Hs[i] = 0.0;
     L.SB[i] = 0.0;
-    L.Hfin[i] = 0.0;
+    L.WP[i] = -1.0;  // the first table build always registers a change
   }
   if (lane == 0) L.misc[0] = 0;  // iteration guard tripped
   __syncthreads();
@@ -244,6 +245,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       base = S.segAs[g] + L.Bacc[a * C + rho];
       capv = L.cap[rho];
     }
+    const double *Ah = L.Ahat + a * C;
     double h = 0.0;
     bool done = !valid;
     for (int it = 0; wave_any(!done); ++it) {
@@ -252,9 +254,18 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         break;
       }
       if (!done) {
-        double nxt = base;
-        const double *Ah = L.Ahat + a * C;
-        for (int k = 0; k < rho; ++k) nxt = fma(mu_term(h, L.K[k], L.rc[k]), Ah[k], nxt);
+        double n0 = base, n1 = 0.0;
+        int k = 0;
+        for (; k + 1 < rho; k += 2) {
+          const double2 q0 = L.KR[k], q1 = L.KR[k + 1];
+          n0 = fma(mu_term(h, q0.x, q0.y), Ah[k], n0);
+          n1 = fma(mu_term(h, q1.x, q1.y), Ah[k + 1], n1);
+        }
+        if (k < rho) {
+          const double2 q0 = L.KR[k];
+          n0 = fma(mu_term(h, q0.x, q0.y), Ah[k], n0);
+        }
+        const double nxt = n0 + n1;
         if (nxt > capv) {
           h = INFINITY;
           done = true;
@@ -269,8 +280,8 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   }
   __syncthreads();
 
-  // ---- sub-chains, pass A: own demand, Lemma 2 sum, Lemma 3 constant,
-  //      overheads, and each callback as a blocking candidate ----
+  // ---- sub-chains: own demand, Lemma 2 sum, Lemma 3 constant, overheads,
+  //      and each callback as a blocking candidate ----
   const bool safe = o.blocking == PAAM_BLOCK_SAFE;
   for (int s = lane; s < nrun; s += kWave) {
     const int64_t rr = run0 + s;
@@ -311,14 +322,15 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       if (((accm >> a) & 1) && L.misc[1 + a] < rho) hp_acc = true;
     double hs0 = delta == 0 ? 0.0 : (hp_acc || o.bound == PAAM_BOUND_L2 ? L2 : A0) + eps;
     if (needL3) hs0 = 0.0;  // a valid start below the fixed point
+    atomicAdd(&L.Hs[e * C + rho], hs0);
     S.r[s] = 0.0;
     S.hs[s] = hs0;
-    S.cst[s] = E;  // blocking added in pass B
+    S.cst[s] = E;  // blocking added below
     S.L2[s] = L2;
     S.A0[s] = A0;
     S.eps[s] = eps;
     S.info0[s] = rho | (e << 16);
-    S.info1[s] = accm | (needL3 ? kNeedL3 : 0) | (delta > 0 ? kHasSeg : 0);
+    S.info1[s] = accm | (needL3 ? kNeedL3 : 0);
   }
   __syncthreads();
   // suffix maximum of blocking candidates per executor, lowest priority up
@@ -330,136 +342,156 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     }
   }
   __syncthreads();
-  // pass B: blocking by one callback of a lower priority chain on the executor
+  // blocking by one callback of a lower priority chain on the executor
   for (int s = lane; s < nrun; s += kWave) {
     const int rho = S.info0[s] & 0xffff;
     const int e = S.info0[s] >> 16;
-    const double B = rho + 1 < C ? L.SB[e * C + rho + 1] : 0.0;
-    S.cst[s] += B;
+    S.cst[s] += rho + 1 < C ? L.SB[e * C + rho + 1] : 0.0;
   }
   __syncthreads();
+  for (int i = lane; i < X * C; i += kWave) L.Pt[i] = -1.0;  // SB is dead from here on
 
-  // ---- Theorem 1 / Eq. (6), executor by executor ----
+  // ---- Theorem 1 / Eq. (6): all sub-chains of the set together ----
   bool missed = false;
-  for (int xi = 0; xi < X && !missed; ++xi) {
-    const int e = b.exec_seq[x0 + xi];
-    const int ne = b.er_cnt[x0 + e];
-    if (ne == 0) continue;
-    const int32_t *runs = b.exec_runs + run0 + b.er_off[x0 + e];
-    const uint32_t hpx = b.hpx_mask[x0 + e];
-    const bool hasP = hpx != 0;
-    // hpp weights: E + spin() summed over the higher executors of the core
-    for (int rho = lane; rho < C; rho += kWave) {
-      double p = 0.0;
-      for (int e2 = 0; e2 < X; ++e2) {
-        if (!((hpx >> e2) & 1u)) continue;
-        const double sp = L.spinf[rho] ? L.Hfin[e2 * C + rho] : L.epsce[e2 * C + rho];
-        p += L.Ece[e2 * C + rho] + sp;
-      }
-      L.P[rho] = p;
-      L.W[rho] = -1.0;  // forces the first comparison to see a change
+  for (int sweep = 0;; ++sweep) {
+    if (sweep >= kMaxIter) {
+      if (lane == 0) L.misc[0] = 1;
+      break;
+    }
+    // weights at the current H*: WP[e][h] = E + H* of h on e (hp term of a
+    // lower-ranked chain) + hpp weight; Pt[e][h] = hpp weight alone, where
+    // hpp weight = sum over higher-priority executors e2 of the core of
+    // E + spin() (H* if h busy-waits, else its epsilon sum)
+    for (int e = lane; e < X; e += kWave) {
+      L.wmin[e] = C;
+      L.pmax[e] = -1;
     }
     __syncthreads();
-    // largest rank among the executor's sub-chains bounds the hp loop
-    int maxrho = 0;
-    for (int i = lane; i < ne; i += kWave) maxrho = max(maxrho, S.info0[runs[i]] & 0xffff);
-    maxrho = wave_max_int(maxrho);
-
-    for (int sweep = 0;; ++sweep) {
-      if (sweep >= kMaxIter) {
-        if (lane == 0) L.misc[0] = 1;
-        break;
+    for (int i = lane; i < X * C; i += kWave) {
+      const int e = i / C, h = i - e * C;
+      const uint32_t hpx = b.hpx_mask[x0 + e];
+      double p = 0.0;
+      for (uint32_t m = hpx; m; m &= m - 1) {
+        const int e2 = __ffs(m) - 1;
+        p += L.Ece[e2 * C + h] + (L.spinf[h] ? L.Hs[e2 * C + h] : L.epsce[e2 * C + h]);
       }
-      // W = E + H* of every chain on this executor at the current iterates
-      for (int rho = lane; rho < C; rho += kWave) L.Hs[rho] = 0.0;
-      __syncthreads();
-      for (int i = lane; i < ne; i += kWave) {
-        const int s = runs[i];
-        atomicAdd(&L.Hs[S.info0[s] & 0xffff], S.hs[s]);
-      }
-      __syncthreads();
-      int wchg = C;
-      for (int rho = lane; rho < C; rho += kWave) {
-        const double w = L.Ece[e * C + rho] + L.Hs[rho];
-        if (w != L.W[rho]) wchg = min(wchg, rho);
-        L.Wn[rho] = w;
-      }
-      wchg = wave_min_int(wchg);
-      __syncthreads();
-      for (int rho = lane; rho < C; rho += kWave) L.W[rho] = L.Wn[rho];
-      __syncthreads();
-
-      bool any_active = false;
-      for (int ib = 0; ib < ne; ib += kWave) {
-        const int i = ib + lane;
-        int s = -1, rho = 0, inf1 = 0;
-        double r = 0.0;
-        bool active = false;
-        if (i < ne) {
-          s = runs[i];
-          rho = S.info0[s] & 0xffff;
-          inf1 = S.info1[s];
-          r = S.r[s];
-          active = !isinf(r) && (!(inf1 & kConv) || rho > wchg);
-        }
-        if (!wave_any(active)) continue;
-        any_active = true;
-        const bool needL3 = (inf1 & kNeedL3) != 0;
-        const int accm = inf1 & 0xff;
-        double I = 0.0, l3 = 0.0;
-        const int hend = hasP ? C : maxrho;
-        for (int h = 0; h < hend; ++h) {
-          const double m = mu_term(r, L.K[h], L.rc[h]);
-          if (h < rho) {
-            I = fma(m, L.W[h], I);
-            if (needL3) {
-              double ah = 0.0;
-              for (int a = 0; a < NA; ++a)
-                if ((accm >> a) & 1) ah += L.Ahat[a * C + h];
-              l3 = fma(m, ah, l3);
-            }
-          }
-          if (hasP && h != rho) I = fma(m, L.P[h], I);
-        }
-        if (active) {
-          double hsn = S.hs[s];
-          if (needL3) {
-            const double L3 = S.A0[s] + l3;
-            hsn = (o.bound == PAAM_BOUND_L3 ? L3 : fmin(S.L2[s], L3)) + S.eps[s];
-          }
-          double rn = S.cst[s] + hsn + I;
-          if (rn > L.cap[rho]) {
-            rn = INFINITY;
-            if (needL3) {
-              // Lemma 3 at an unbounded window: unbounded iff an HP request
-              // of positive length can interfere (then l3 > 0 already)
-              const double L3i = l3 > 0.0 ? INFINITY : S.A0[s];
-              hsn = (o.bound == PAAM_BOUND_L3 ? L3i : fmin(S.L2[s], L3i)) + S.eps[s];
-            }
-          }
-          S.info1[s] = (inf1 & ~kConv) | (rn == r ? kConv : 0);
-          S.r[s] = rn;
-          S.hs[s] = hsn;
-        }
-      }
-      __syncthreads();
-      if (!any_active && wchg == C && sweep > 0) break;
+      const double wp = L.Ece[i] + L.Hs[i] + p;
+      if (wp != L.WP[i]) atomicMin(&L.wmin[e], h);
+      if (p != L.Pt[i]) atomicMax(&L.pmax[e], h);
+      L.WP[i] = wp;
+      L.Pt[i] = p;
     }
+    __syncthreads();
 
-    // the executor is solved: H* per chain on it, partial end-to-end sums
-    for (int rho = lane; rho < C; rho += kWave) L.Hfin[e * C + rho] = L.Hs[rho];
-    for (int i = lane; i < ne; i += kWave) {
-      const int s = runs[i];
-      atomicAdd(&L.partial[S.info0[s] & 0xffff], S.r[s]);
+    // compact the sub-chains to evaluate: not converged, or a weight they
+    // read changed (WP of a higher rank, Pt of a lower rank)
+    int nact = 0;
+    for (int sb = 0; sb < nrun; sb += kWave) {
+      const int s = sb + lane;
+      bool act = false;
+      if (s < nrun) {
+        const int i0 = S.info0[s];
+        const int rho = i0 & 0xffff, e = i0 >> 16;
+        act = !isinf(S.r[s]) &&
+              (!(S.info1[s] & kConv) || rho > L.wmin[e] || rho < L.pmax[e]);
+      }
+      const unsigned long long m = __ballot(act);
+      if (act) S.alist[nact + (int)__popcll(m & ((1ull << lane) - 1ull))] = s;
+      nact += (int)__popcll(m);
+    }
+    if (nact == 0) break;
+    __syncthreads();
+
+    for (int ib = 0; ib < nact; ib += kWave) {
+      const int i = ib + lane;
+      const bool valid = i < nact;
+      int s = 0, rho = 0, e = 0, inf1 = 0;
+      double r = 0.0;
+      if (valid) {
+        s = S.alist[i];
+        const int i0 = S.info0[s];
+        rho = i0 & 0xffff;
+        e = i0 >> 16;
+        inf1 = S.info1[s];
+        r = S.r[s];
+      }
+      const bool hasP = valid && b.hpx_mask[x0 + e] != 0;
+      const int hend = wave_max_int(valid ? (hasP ? C : rho) : 0);
+      const bool needL3 = (inf1 & kNeedL3) != 0;
+      const int accm = inf1 & 0xff;
+      const double *wp = L.WP + e * C;
+      const double *pt = L.Pt + e * C;
+      double I0 = 0.0, I1 = 0.0, l3 = 0.0;
+      int h = 0;
+      for (; h + 1 < hend; h += 2) {
+        const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
+        const double m0 = mu_term(r, q0.x, q0.y);
+        const double m1 = mu_term(r, q1.x, q1.y);
+        double w0 = h < rho ? wp[h] : pt[h];
+        double w1 = h + 1 < rho ? wp[h + 1] : pt[h + 1];
+        w0 = h == rho ? 0.0 : w0;
+        w1 = h + 1 == rho ? 0.0 : w1;
+        I0 = fma(m0, w0, I0);
+        I1 = fma(m1, w1, I1);
+        if (needL3 && h < rho) {
+          double a0s = 0.0, a1s = 0.0;
+          for (int a = 0; a < NA; ++a)
+            if ((accm >> a) & 1) {
+              a0s += L.Ahat[a * C + h];
+              a1s += h + 1 < rho ? L.Ahat[a * C + h + 1] : 0.0;
+            }
+          l3 = fma(m0, a0s, l3);
+          l3 = fma(m1, a1s, l3);
+        }
+      }
+      if (h < hend) {
+        const double2 q0 = L.KR[h];
+        const double m0 = mu_term(r, q0.x, q0.y);
+        double w0 = h < rho ? wp[h] : pt[h];
+        w0 = h == rho ? 0.0 : w0;
+        I0 = fma(m0, w0, I0);
+        if (needL3 && h < rho) {
+          double a0s = 0.0;
+          for (int a = 0; a < NA; ++a)
+            if ((accm >> a) & 1) a0s += L.Ahat[a * C + h];
+          l3 = fma(m0, a0s, l3);
+        }
+      }
+      if (valid) {
+        const double hs_old = S.hs[s];
+        double hsn = hs_old;
+        if (needL3) {
+          const double L3 = S.A0[s] + l3;
+          hsn = (o.bound == PAAM_BOUND_L3 ? L3 : fmin(S.L2[s], L3)) + S.eps[s];
+        }
+        double rn = S.cst[s] + hsn + (I0 + I1);
+        if (rn > L.cap[rho]) {
+          rn = INFINITY;
+          if (needL3) {
+            // Lemma 3 at an unbounded window: unbounded iff an HP request of
+            // positive length can interfere (then l3 > 0 already)
+            const double L3i = l3 > 0.0 ? INFINITY : S.A0[s];
+            hsn = (o.bound == PAAM_BOUND_L3 ? L3i : fmin(S.L2[s], L3i)) + S.eps[s];
+          }
+        }
+        if (hsn != hs_old) atomicAdd(&L.Hs[e * C + rho], hsn - hs_old);
+        if (rn != r) atomicAdd(&L.partial[rho], rn - r);
+        S.info1[s] = (inf1 & ~kConv) | (rn == r ? kConv : 0);
+        S.r[s] = rn;
+        S.hs[s] = hsn;
+      }
     }
     __syncthreads();
     if (!full) {
+      // every iterate is a lower bound: a partial end-to-end sum above the
+      // deadline proves the miss
       bool miss = false;
-      for (int rho = lane; rho < C; rho += kWave) {
-        const double lb = L.partial[rho] + (double)(L.nrun[rho] - 1) * hop;
-        if (lb > L.Dd[rho]) miss = true;
+      for (int rho = lane; rho < C; rho += kWave)
+        if (L.partial[rho] + (double)(L.nrun[rho] - 1) * hop > L.Dd[rho]) miss = true;
+      if (wave_any(miss)) {
+        missed = true;
+        break;
       }
-      missed = wave_any(miss);
     }
   }
 
@@ -482,13 +514,11 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     int64_t wR = PAAM_INF;
     if (!missed && (ok || full)) {
       for (int c = 0; c < C; ++c) {
-        const int rho = L.rank[c];
         if (w < 0) {
           w = c;
           continue;
         }
-        const int rw = L.rank[w];
-        if (ratio_gt(L.partial[rho], b.D[c0 + c], L.partial[rw], b.D[c0 + w])) w = c;
+        if (ratio_gt(L.partial[L.rank[c]], b.D[c0 + c], L.partial[L.rank[w]], b.D[c0 + w])) w = c;
       }
       const double R = L.partial[L.rank[w]];
       wR = isinf(R) ? PAAM_INF : (int64_t)R;
@@ -517,17 +547,123 @@ __global__ __launch_bounds__(kWave) void wcrt_kernel(WcrtLaunch L) {
   }
 }
 
+// ---------------------------- priority search ------------------------------
+
+// SplitMix64 [Steele, Lea & Flood 2014]: the output function, and output m of
+// the stream of a set, whose state starts at mix(seed + G*(set+1)) and
+// advances by G per output.
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t swap_stream(uint64_t seed, int64_t set, uint64_t m) {
+  const uint64_t G = 0x9E3779B97F4A7C15ull;
+  return splitmix_mix(splitmix_mix(seed + G * (uint64_t)(set + 1)) + G * (m + 1));
+}
+
+// Per-wave search state after the analysis scratch: the verdict slot, the
+// candidate order (chain at each rank) and the ranks of the chains.
+struct SearchSlot {
+  int64_t *worst_R;  // [1]
+  int32_t *worst;    // [1]
+  int8_t *sched;     // [1]
+  int32_t *order;    // [max_C]
+  int16_t *rank;     // [max_C]
+};
+
+__device__ SearchSlot carve_slot(unsigned char *base, int Cm) {
+  SearchSlot q;
+  q.worst_R = reinterpret_cast<int64_t *>(base);
+  q.worst = reinterpret_cast<int32_t *>(base + 8);
+  q.sched = reinterpret_cast<int8_t *>(base + 12);
+  q.order = reinterpret_cast<int32_t *>(base + 16);
+  q.rank = reinterpret_cast<int16_t *>(base + 16 + 4 * (size_t)Cm);
+  return q;
+}
+
+// Plain priority-order search.  Candidate 0 is the uploaded order; candidate
+// k >= 1 is candidate k-1 with the positions i = u1 mod C and
+// j = (i + 1 + u2 mod (C-1)) mod C swapped (u1, u2 = outputs 2k-2, 2k-1 of the
+// set's stream).  Each candidate is analysed by analyse_set in verdict mode,
+// reading the candidate's ranks through the batch's rank table; the first
+// feasible k is the smallest one.
+__global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
+  unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
+  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs);
+  SearchSlot q = carve_slot(wbase + L.analysis_stride, L.b.max_C);
+  paam_wcrt_opts o = L.o.wcrt;
+  o.full = 0;
+  for (;;) {
+    unsigned long long i = 0;
+    if (threadIdx.x == 0) i = atomicAdd(L.counter, 1ull);
+    i = __shfl(i, 0);
+    if (i >= (unsigned long long)L.b.n_sets) break;
+    const int64_t set = L.b.work_order[i];
+    const int64_t c0 = L.b.set_chain_off[set];
+    const int C = (int)(L.b.set_chain_off[set + 1] - c0);
+    for (int c = threadIdx.x; c < C; c += kWave) {
+      const int r = L.b.rank0[c0 + c];
+      q.order[r] = c;
+      q.rank[c] = (int16_t)r;
+    }
+    __syncthreads();
+    // the analysis reads rank0[c0 + c]: point it at this wave's candidate ranks
+    DevBatch bq = L.b;
+    bq.rank0 = q.rank - c0;
+    int found = -1, n_eval = 0;
+    for (int k = 0; k < L.o.n_cand; ++k) {
+      if (k > 0 && C >= 2) {
+        if (threadIdx.x == 0) {
+          const uint64_t u1 = swap_stream(L.o.seed, set, 2 * (uint64_t)(k - 1));
+          const uint64_t u2 = swap_stream(L.o.seed, set, 2 * (uint64_t)(k - 1) + 1);
+          const int pa = (int)(u1 % (uint64_t)C);
+          const int pb = (int)((pa + 1 + (int64_t)(u2 % (uint64_t)(C - 1))) % C);
+          const int ca = q.order[pa], cb = q.order[pb];
+          q.order[pa] = cb;
+          q.order[pb] = ca;
+          q.rank[cb] = (int16_t)pa;
+          q.rank[ca] = (int16_t)pb;
+        }
+        __syncthreads();
+      }
+      analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+      ++n_eval;
+      int v = 0;
+      if (threadIdx.x == 0) v = q.sched[0];  // written by lane 0 of analyse_set
+      v = __shfl(v, 0);
+      if (v != 0) {
+        found = v > 0 ? k : -2;
+        break;
+      }
+    }
+    if (threadIdx.x == 0) {
+      L.found[set] = found;
+      L.n_exact[set] = n_eval;
+    }
+    if (L.found_prio && found >= 0)
+      for (int r = threadIdx.x; r < C; r += kWave) L.found_prio[c0 + q.order[r]] = C - r;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 size_t wave_scratch_bytes(const DevBatch &b) {
   size_t n = (size_t)b.max_segs * 2 * sizeof(double) + (size_t)b.max_runs * 6 * sizeof(double) +
-             (size_t)b.max_runs * 2 * sizeof(int32_t);
+             (size_t)b.max_runs * 3 * sizeof(int32_t);
   return (n + 255) & ~(size_t)255;
+}
+
+size_t wave_search_bytes(const DevBatch &b) {
+  return wave_scratch_bytes(b) + ((16 + 6 * (size_t)b.max_C + 255) & ~(size_t)255);
 }
 
 size_t wave_lds_bytes(const DevBatch &b) {
   const size_t Cm = b.max_C, Xm = b.max_X, NAm = b.max_NA > 0 ? b.max_NA : 1;
-  return 8 * (9 * Cm + 3 * NAm * Cm + 4 * Xm * Cm) + 4 * (4 * Cm + 2 * NAm * Cm + 16);
+  return 8 * (5 * Cm + 3 * NAm * Cm + 5 * Xm * Cm) + 4 * (4 * Cm + 2 * NAm * Cm + 2 * Xm + 16);
 }
 
 int launch_wcrt(const WcrtLaunch &L, void *stream) {
@@ -537,6 +673,16 @@ int launch_wcrt(const WcrtLaunch &L, void *stream) {
   if (e != hipSuccess) return (int)e;
   if (L.b.n_sets == 0) return 0;
   hipLaunchKernelGGL(wcrt_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  return (int)hipGetLastError();
+}
+
+int launch_search(const SearchLaunch &L, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, L.counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  if (L.b.n_sets == 0) return 0;
+  hipLaunchKernelGGL(search_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
 }
 

@@ -1,0 +1,56 @@
+"""GPU parity of paam_priority_search against the oracle's plain search.
+
+The found candidate index must equal the oracle's smallest feasible k, the
+number of exact analyses must match, and the reported priorities must be the
+oracle's candidate order for that k."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_06452_amd import chaingen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def paam():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_06452_amd import _paam
+    return _paam
+
+
+def check(paam, cs, n_cand, seed, **kw):
+    dev = paam.Chainset(cs)
+    g = paam.search(dev, n_cand, seed, **kw)
+    r = oracle.search(cs, n_cand, seed, threads=8, **kw)
+    assert np.array_equal(g["found"], r["found"]), np.nonzero(g["found"] != r["found"])[0][:10]
+    assert np.array_equal(g["n_exact"], r["n_eval"])
+    for s in np.nonzero(g["found"] >= 0)[0][:200]:
+        c0, c1 = cs.set_chain_off[s], cs.set_chain_off[s + 1]
+        order = oracle.candidate_order(cs, int(s), seed, int(g["found"][s]))
+        want = np.zeros(c1 - c0, np.int32)
+        want[order] = (c1 - c0) - np.arange(c1 - c0)
+        assert g["found_prio"][c0:c1].tolist() == want.tolist()
+    return g
+
+
+def test_search_matches_oracle_low_utilisation(paam):
+    p = chaingen.PRESETS["search"].replace(util=(0.02, 0.12), seed=91)
+    g = check(paam, chaingen.generate(p, 3000), 64, 4242)
+    print("found", (g["found"] >= 0).mean(), "found after k=0", (g["found"] > 0).mean(), flush=True)
+    assert (g["found"] > 0).sum() >= 1
+
+
+def test_search_matches_oracle_search_preset(paam):
+    check(paam, chaingen.generate("search", 500), 256, 777)
+
+
+def test_search_matches_oracle_varied_sets(paam):
+    p = chaingen.PRESETS["small"].replace(seed=93, chains=(1, 10), cbs=(1, 4), n_exec=3,
+                                          util=(0.02, 0.3), T=(20.0, 4000.0), n_buckets=2,
+                                          eps=1, kappa=1, eps_hop=1)
+    check(paam, chaingen.generate(p, 2000), 40, 99, blocking=1)
+    check(paam, chaingen.generate(p, 2000), 40, 98, cap_mult=2)
