@@ -40,6 +40,47 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+# HBM bytes per full-mode launch of the analysis kernel on the default
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled
+# by the counters' reading for the 1 GiB calibration copy.  Valid only for the
+# kernel source with this SHA-256; reported as null for any other.
+TRAFFIC = {"sha256": "79dacb323eb31a7063da12404526ee880d8608e813a2da7640c734d838e65e32",
+           "bytes_per_launch": 38.66e9, "sets": 1_000_000}
+KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
+
+COPY_BYTES = 1 << 30
+
+
+def measured_traffic(n_sets):
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != TRAFFIC["sha256"] or n_sets != TRAFFIC["sets"]:
+        return None
+    return TRAFFIC["bytes_per_launch"]
+
+
+def copy_calibration(torch, stream):
+    """A plain device-to-device copy of COPY_BYTES: its measured rate is the
+    attainable HBM bandwidth, and in a counter profile of this script its
+    FETCH_SIZE / WRITE_SIZE per dispatch (COPY_BYTES each way) give the
+    counters' scale."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(5):
+            dst.copy_(src)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 5
+    del src, dst
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +112,8 @@ def main():
         dev.arena.numel() / 1e9, dev.n_subchains, time.perf_counter() - t0))
 
     stream = torch.cuda.Stream()
+    copy_gbs = copy_calibration(torch, stream)
+    log("plain device copy: %.0f GB/s (read + write)" % copy_gbs)
     opts = [_paam.wcrt_opts(full=True, util_permille=u, waves_per_cu=args.waves_per_cu)
             for u in levels]
     ws = _paam.workspace(max(_paam.paam_wcrt_bytes(dev, o) for o in opts))
@@ -189,9 +232,10 @@ def main():
             "peak": PEAK_TERMS / 1e9,
             "unit": "Gterm/s",
             "frac": achieved / PEAK_TERMS,
-            "traffic": None,
+            "traffic": measured_traffic(cs.n_sets),
             "kernel": "wcrt_kernel",
             "avg_launch_ms": launch_ms,
+            "copy_GBps_measured": copy_gbs,
             "terms_per_analysis": float(np.mean(terms_per_level)),
         },
         "cpu_baseline": {
