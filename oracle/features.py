@@ -203,8 +203,12 @@ def chain_features(st: dict, order, util_permille: int = 1000) -> np.ndarray:
                         q_hpp += q[h][e2] + (qa[h][e2] if spin[h] else 0)
         f[30] = ratio(n_hpp, D[c])
         f[31] = ratio(q_hpp, Q)
-        # accelerators (Eq. (3) and (4))
-        n_acc = sum(2 * dca[c][a] * Ahat[h][a] for a in uses for h in HP)
+        # accelerators (Eq. (3) and (4)): two requests of every HP chain on
+        # each accelerator a sub-chain uses, once per sub-chain
+        n_acc = 0
+        for e, ids in _runs(chains[c]["cbs"]):
+            acc_s = sorted({acc for j in ids for (_a, acc) in chains[c]["cbs"][j]["segs"]})
+            n_acc += sum(2 * Ahat[h][a] for a in acc_s for h in HP)
         f[32] = ratio(n_acc, D[c])
         f[33] = ratio(sum(qA[h][a] for a in uses for h in HP), Q)
         n_bacc = 0
@@ -223,9 +227,10 @@ def chain_features(st: dict, order, util_permille: int = 1000) -> np.ndarray:
         f[42] = ratio(X, 8)
         f[43] = ratio(NA, 8)
         f[44] = ratio(min(T), T[c])
-        # floor estimates of the bound: own demand + carry-in + blocking + hpp
-        # + accelerator carry-in, then the same plus the utilisation terms
-        n_est = own + n_carry + n_bs + n_hpp + n_acc
+        # a floor of the bound: own demand, two jobs of every interfering chain
+        # per sub-chain (hp, hpp, accelerator), SAFE blocking and same-bucket
+        # blocking; then the same plus the utilisation terms
+        n_est = own + n_carry + n_bs + n_hpp + n_acc + n_bacc
         f[45] = ratio(n_est, D[c])
         q_est = (sum(q[h][e] for e in mine for h in HP) + sum(qa[h][e] for e in mine for h in HP)
                  + q_hpp + sum(qA[h][a] for a in uses for h in HP))

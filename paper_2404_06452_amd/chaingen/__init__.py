@@ -292,3 +292,45 @@ def generate(params: GenParams | str, n_sets: int, set_begin: int = 0,
         if rc != 0:
             raise RuntimeError("chaingen_fill failed (%d)" % rc)
     return cs
+
+
+# ------------------------------------------------- random inputs of the ranking
+# Draws that the surrogate part consumes as inputs: initial network parameters,
+# the (set, candidate) pairs of a training run, and synthetic score vectors.
+# Parameter layout: W1 [256][48] | b1 [256] | W2 [256][256] | b2 [256] |
+# w3 [256] | b3 [1] (78,593 float32 values).
+MLP_SHAPES = (((256, 48), 48), ((256,), 0), ((256, 256), 256), ((256,), 0), ((256,), 256),
+              ((1,), 0))
+MLP_PARAMS = 78593
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """He-uniform weights (limit sqrt(6 / fan_in)) and zero biases, float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, fan_in in MLP_SHAPES:
+        if fan_in == 0:
+            parts.append(np.zeros(shape))
+        else:
+            lim = np.sqrt(6.0 / fan_in)
+            parts.append(rng.uniform(-lim, lim, size=shape))
+    out = np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+    assert out.size == MLP_PARAMS
+    return out
+
+
+def training_pairs(n_sets: int, n_samples: int, n_cand: int, seed: int) -> np.ndarray:
+    """int64 [n_samples, 2]: (set, candidate k) drawn uniformly."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((n_samples, 2), np.int64)
+    out[:, 0] = rng.integers(0, n_sets, n_samples)
+    out[:, 1] = rng.integers(0, n_cand, n_samples)
+    return out
+
+
+def random_scores(n: int, seed: int, ties: bool = False) -> np.ndarray:
+    """float32 [n] synthetic scores; with ``ties`` drawn from 8 values only."""
+    rng = np.random.default_rng(seed)
+    if ties:
+        return rng.integers(0, 8, n).astype(np.float32) / 4.0
+    return rng.uniform(0.0, 2.0, n).astype(np.float32)
