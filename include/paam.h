@@ -77,8 +77,8 @@ paam_status paam_chainset_bytes(const paam_chainset_host *h, size_t *arena_bytes
 
 /* Validates the batch, derives its priority-independent structure
  * (sub-chains = maximal runs of consecutive callbacks on one executor,
- * executor order per core, reciprocals of the periods, a longest-first work
- * order) and copies it into the caller's device arena (>= arena_bytes, 256-B
+ * executors of the same core with higher process priority, reciprocals of the
+ * periods, a longest-first work order) and copies it into the caller's device arena (>= arena_bytes, 256-B
  * aligned).  Blocks until the copy is done.  *out must be released with
  * paam_chainset_free; the arena must outlive it.  Limits per set: 1..4096
  * chains, 1..32 executors, 0..8 accelerators, 65535 sub-chains; every time
@@ -157,6 +157,99 @@ paam_status paam_search_bytes(const paam_chainset *cs, const paam_search_opts *o
 paam_status paam_priority_search(const paam_chainset *cs, const paam_search_opts *o,
                                  int32_t *found, int32_t *n_exact, int32_t *found_prio, void *d_ws,
                                  size_t ws_bytes, paam_stream stream);
+
+/* ---------------- candidate-ranking surrogate ----------------------------
+ * A learned ranking of candidate orders sits on top of the analysis: the exact
+ * analysis above stays the sole judge of schedulability; the network only
+ * decides which candidates reach it first.  None of it is part of the paper's
+ * method.  A "pair" names one candidate order of one set and the utilisation
+ * scale to analyse it at: int64 triples (set, k, util_permille), k as in the
+ * search above (0 = uploaded order, k >= 1 = k swaps along the set's walk,
+ * with the seed given to the call). */
+#define PAAM_FEATURES 48      /* features per chain */
+#define PAAM_MLP_HIDDEN 256   /* hidden units of both hidden layers */
+#define PAAM_MLP_PARAMS 78593 /* float32 master parameters */
+#define PAAM_MLP_PACKED 82176 /* bfloat16 packed weights (uint16 values) */
+
+/* Workspace for paam_candidate_wcrt on n_pairs pairs. */
+paam_status paam_candidate_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, int64_t n_pairs,
+                                 size_t *ws_bytes);
+
+/* Exact analysis of explicit candidate orders (Sec. IV-F, every chain's bound
+ * at cap o->cap_mult * D; o->full and o->util_permille are ignored: each pair
+ * carries its own scale).  Outputs per pair (device):
+ *   sched [n]    1 if every chain meets its deadline, 0 if not, -1 on the guard
+ *   worst_R [n]  bound of the chain with the largest R/D (ties: lowest index),
+ *                PAAM_INF past its cap
+ *   worst_D [n]  that chain's deadline
+ *   ratio [n]    min(worst_R / worst_D, cap_mult) as float (cap_mult when INF);
+ *                the training target of the ranking network
+ * Pairs must name existing sets, 0 <= k < 2^31 and util_permille >= 0
+ * (checked on the device; a bad pair yields sched = -2). */
+paam_status paam_candidate_wcrt(const paam_chainset *cs, const paam_wcrt_opts *o, uint64_t seed,
+                                const int64_t *d_pairs, int64_t n_pairs, int8_t *sched,
+                                int64_t *worst_R, int64_t *worst_D, float *ratio, void *d_ws,
+                                size_t ws_bytes, paam_stream stream);
+
+/* Workspace for paam_features. */
+paam_status paam_features_bytes(const paam_chainset *cs, int64_t n_pairs, size_t *ws_bytes);
+
+/* Per-chain features of candidate orders, 48 per chain (bfloat16 bit
+ * patterns).  Pair i owns rows [i*row_stride, i*row_stride + C_i) of feat
+ * ([n_pairs*row_stride][48], row_stride >= the largest set of the batch);
+ * count[i] = C_i.  Rows past C_i are left untouched.  Every feature is a ratio
+ * of exact integers rounded once to double, then to float and to bfloat16
+ * (round to nearest even); utilisation terms are floor(x * 2^16 / T).
+ * PAAM_E_RANGE if a set's total demand reaches 2^40 ns at the largest scale. */
+paam_status paam_features(const paam_chainset *cs, uint64_t seed, const int64_t *d_pairs,
+                          int64_t n_pairs, int32_t row_stride, uint16_t *feat, int32_t *count,
+                          void *d_ws, size_t ws_bytes, paam_stream stream);
+
+/* The network: per chain row x (48), z1 = W1 x + b1, h1 = max(z1, 0); per
+ * candidate p = mean of h1 over its rows, z2 = W2 p + b2, h2 = max(z2, 0),
+ * y = w3 . h2 + b3 (the predicted largest R/D).  float32 master parameters,
+ * layout W1 [256][48] | b1 [256] | W2 [256][256] | b2 [256] | w3 [256] | b3.
+ * Products take bfloat16 operands (x, W1, W2, w3, p, h2, each rounded to
+ * nearest even) and accumulate in float32, W1 x and W2 p on the matrix cores.
+ * Packed weights (uint16 bfloat16 patterns): W1 [256][64] (columns 48..63
+ * zero) | W2 [256][256] | w3 [256]. */
+paam_status paam_mlp_pack(const float *d_params, uint16_t *d_packed, paam_stream stream);
+
+/* Forward over n candidates whose features paam_features wrote (row_stride,
+ * count as there).  out [n] = y.  act (may be NULL) receives what the
+ * backward pass needs: n * 1024 bytes (p and h2 as bfloat16). */
+paam_status paam_mlp_forward(const float *d_params, const uint16_t *d_packed,
+                             const uint16_t *feat, const int32_t *count, int64_t n,
+                             int32_t row_stride, float *out, void *act, paam_stream stream);
+
+/* Workspace for paam_mlp_backward. */
+paam_status paam_mlp_backward_bytes(int64_t n, size_t *ws_bytes);
+
+/* Gradient of the mean squared error (1/n) sum (y - target)^2 with respect to
+ * the master parameters (straight through the bfloat16 roundings), float32,
+ * reduced in a fixed order (deterministic).  grad [78593]; loss [1]. */
+paam_status paam_mlp_backward(const float *d_params, const uint16_t *d_packed,
+                              const uint16_t *feat, const int32_t *count, int64_t n,
+                              int32_t row_stride, const float *out, const float *target,
+                              const void *act, float *grad, float *loss, void *d_ws,
+                              size_t ws_bytes, paam_stream stream);
+
+/* One Adam step (Kingma & Ba 2015, with bias correction; step counts from 1)
+ * on the float32 master parameters and moments, then repacks the bfloat16
+ * weights. */
+paam_status paam_mlp_adam_step(float *d_params, uint16_t *d_packed, float *d_m, float *d_v,
+                               const float *grad, float lr, float beta1, float beta2, float eps,
+                               int64_t step, paam_stream stream);
+
+/* Workspace for paam_score_candidates. */
+paam_status paam_score_bytes(const paam_chainset *cs, const paam_search_opts *o, size_t *ws_bytes);
+
+/* Scores every candidate of every set with the network: scores
+ * [n_sets * n_cand] (set-major), the input of a guided search with the same
+ * options.  Features and forward run in chunks inside the workspace. */
+paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opts *o,
+                                  const float *d_params, const uint16_t *d_packed, float *scores,
+                                  void *d_ws, size_t ws_bytes, paam_stream stream);
 
 /* Thread-local description of the last failure ("" if none). */
 const char *paam_last_error(void);

@@ -215,3 +215,68 @@ def search(cs, n_cand, seed, blocking=BLOCK_SAFE, cap_mult=1, util_permille=1000
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(run, [(lo + a, lo + b_) for a, b_ in _ranges(hi - lo, 8 * threads)]))
     return {"found": found, "n_eval": n_eval, "terms": terms}
+
+
+def candidate_analysis(cs, pairs, seed, cap_mult=2, blocking=BLOCK_SAFE, bound=BOUND_MIN):
+    """Exact analysis of (set, k, util_permille) triples: every chain's bound
+    at cap cap_mult * D under candidate order k.  Returns sched, worst_R,
+    worst_D and ratio = min(worst_R / worst_D, cap_mult) rounded to float32."""
+    pairs = np.asarray(pairs, np.int64).reshape(-1, 3)
+    n = len(pairs)
+    out = {"sched": np.zeros(n, np.int8), "worst_R": np.zeros(n, np.int64),
+           "worst_D": np.zeros(n, np.int64), "ratio": np.zeros(n, np.float32)}
+    for i, (s, k, u) in enumerate(pairs):
+        order = candidate_order(cs, int(s), seed, int(k))
+        r = analyse_set(cs, int(s), order=order, full=True, cap_mult=cap_mult,
+                        util_permille=int(u), blocking=blocking, bound=bound)
+        c0 = int(cs.set_chain_off[s])
+        w = r["worst"]
+        D = int(cs.D[c0 + w])
+        out["sched"][i] = r["sched"]
+        out["worst_R"][i] = r["worst_R"]
+        out["worst_D"][i] = D
+        ratio = float(cap_mult) if r["worst_R"] == INF else min(float(r["worst_R"]) / float(D),
+                                                                 float(cap_mult))
+        out["ratio"][i] = np.float32(ratio)
+    return out
+
+
+def score_order(scores):
+    """Candidate indices by ascending score, ties to the lower index; -0.0
+    sorts before +0.0 and every NaN after all numbers (IEEE total order on
+    the float32 values)."""
+    s = np.asarray(scores, np.float32)
+    keys = []
+    for k, v in enumerate(s):
+        if np.isnan(v):
+            key = (1, 0.0, 0)
+        else:
+            key = (0, float(v), 0 if (v == 0.0 and np.signbit(v)) else 1)
+        keys.append((key, k))
+    return [k for _, k in sorted(keys)]
+
+
+def guided_search(cs, n_cand, seed, scores, top_k, fallback=True, blocking=BLOCK_SAFE,
+                  util_permille=1000, sets=None):
+    """Guided search: the top_k candidates by score (score_order) analysed in
+    that order; the first feasible one wins.  With fallback, the remaining
+    candidates follow in index order.  scores: [n_sets * n_cand]."""
+    scores = np.asarray(scores, np.float32).reshape(-1, n_cand)
+    n = int(cs.n_sets)
+    lo, hi = (0, n) if sets is None else sets
+    found = np.full(n, -1, np.int32)
+    n_eval = np.zeros(n, np.int32)
+    for s in range(lo, hi):
+        top = score_order(scores[s])[:min(top_k, n_cand)]
+        seq = list(top)
+        if fallback:
+            chosen = set(top)
+            seq += [k for k in range(n_cand) if k not in chosen]
+        for k in seq:
+            r = analyse_set(cs, s, order=candidate_order(cs, s, seed, k), full=False,
+                            util_permille=util_permille, blocking=blocking)
+            n_eval[s] += 1
+            if r["sched"] != 0:
+                found[s] = k if r["sched"] > 0 else -2
+                break
+    return {"found": found, "n_eval": n_eval}

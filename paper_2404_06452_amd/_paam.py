@@ -23,8 +23,14 @@ PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
 EXPORTED = (
     "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
     "paam_wcrt_bytes", "paam_wcrt_batch", "paam_search_bytes", "paam_priority_search",
+    "paam_candidate_bytes", "paam_candidate_wcrt", "paam_features_bytes", "paam_features",
+    "paam_mlp_pack", "paam_mlp_forward", "paam_mlp_backward_bytes", "paam_mlp_backward",
+    "paam_mlp_adam_step", "paam_score_bytes", "paam_score_candidates",
     "paam_last_error", "paam_version",
 )
+N_FEAT = 48
+MLP_PARAMS = 78593
+MLP_PACKED = 82176
 
 
 class PaamError(RuntimeError):
@@ -71,6 +77,25 @@ def lib():
         L.paam_wcrt_batch.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P, S, P]
         L.paam_search_bytes.argtypes = [P, ctypes.POINTER(paam_search_opts), ctypes.POINTER(S)]
         L.paam_priority_search.argtypes = [P, ctypes.POINTER(paam_search_opts), P, P, P, P, S, P]
+        I64, I32, U64, F = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_float
+        L.paam_candidate_bytes.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), I64,
+                                           ctypes.POINTER(S)]
+        L.paam_candidate_wcrt.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), U64, P, I64, P, P, P,
+                                          P, P, S, P]
+        L.paam_features_bytes.argtypes = [P, I64, ctypes.POINTER(S)]
+        L.paam_features.argtypes = [P, U64, P, I64, I32, P, P, P, S, P]
+        L.paam_mlp_pack.argtypes = [P, P, P]
+        L.paam_mlp_forward.argtypes = [P, P, P, P, I64, I32, P, P, P]
+        L.paam_mlp_backward_bytes.argtypes = [I64, ctypes.POINTER(S)]
+        L.paam_mlp_backward.argtypes = [P, P, P, P, I64, I32, P, P, P, P, P, P, S, P]
+        L.paam_mlp_adam_step.argtypes = [P, P, P, P, P, F, F, F, F, I64, P]
+        L.paam_score_bytes.argtypes = [P, ctypes.POINTER(paam_search_opts), ctypes.POINTER(S)]
+        L.paam_score_candidates.argtypes = [P, ctypes.POINTER(paam_search_opts), P, P, P, P, S, P]
+        for f in ("paam_candidate_bytes", "paam_candidate_wcrt", "paam_features_bytes",
+                  "paam_features", "paam_mlp_pack", "paam_mlp_forward", "paam_mlp_backward_bytes",
+                  "paam_mlp_backward", "paam_mlp_adam_step", "paam_score_bytes",
+                  "paam_score_candidates"):
+            getattr(L, f).restype = ctypes.c_int32
         L.paam_last_error.argtypes = []
         L.paam_last_error.restype = ctypes.c_char_p
         L.paam_version.argtypes = []
@@ -196,7 +221,7 @@ def wcrt(cs: Chainset, stream=None, **kw) -> dict:
     out = WcrtOut(cs, bool(o.full))
     ws = workspace(paam_wcrt_bytes(cs, o), cs.device)
     paam_wcrt_batch(cs, o, out, ws, stream)
-    torch.cuda.synchronize()
+    _sync(cs.device)
     res = {"sched": out.set_sched.cpu().numpy(), "worst": out.set_worst.cpu().numpy(),
            "worst_R": out.set_worst_R.cpu().numpy()}
     if out.chain_R is not None:
@@ -246,6 +271,163 @@ def search(cs: Chainset, n_cand: int, seed: int, stream=None, scores=None, guide
     out = SearchOut(cs)
     ws = workspace(paam_search_bytes(cs, o), cs.device)
     paam_priority_search(cs, o, out, ws, stream)
-    torch.cuda.synchronize()
+    _sync(cs.device)
     return {"found": out.found.cpu().numpy(), "n_exact": out.n_exact.cpu().numpy(),
             "found_prio": out.found_prio.cpu().numpy()[:cs.n_chains]}
+
+
+# ------------------------------------------------------------ candidate ranking
+
+def _size(fn, *args) -> int:
+    n = ctypes.c_size_t(0)
+    check(getattr(lib(), fn)(*args, ctypes.byref(n)), fn)
+    return int(n.value)
+
+
+def paam_candidate_bytes(cs: Chainset, opts: paam_wcrt_opts, n_pairs: int) -> int:
+    return _size("paam_candidate_bytes", cs.handle, ctypes.byref(opts), n_pairs)
+
+
+class CandOut:
+    def __init__(self, n: int, device):
+        import torch
+        self.sched = torch.empty(max(n, 1), dtype=torch.int8, device=device)
+        self.worst_R = torch.empty(max(n, 1), dtype=torch.int64, device=device)
+        self.worst_D = torch.empty(max(n, 1), dtype=torch.int64, device=device)
+        self.ratio = torch.empty(max(n, 1), dtype=torch.float32, device=device)
+
+
+def paam_candidate_wcrt(cs: Chainset, opts: paam_wcrt_opts, seed: int, pairs, out: CandOut, ws,
+                        stream=None) -> None:
+    n = int(pairs.shape[0])
+    check(lib().paam_candidate_wcrt(cs.handle, ctypes.byref(opts), seed & (2**64 - 1),
+                                    pairs.data_ptr(), n, out.sched.data_ptr(),
+                                    out.worst_R.data_ptr(), out.worst_D.data_ptr(),
+                                    out.ratio.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream_ptr(stream)),
+          "paam_candidate_wcrt")
+
+
+def paam_features_bytes(cs: Chainset, n_pairs: int) -> int:
+    return _size("paam_features_bytes", cs.handle, n_pairs)
+
+
+def paam_features(cs: Chainset, seed: int, pairs, row_stride: int, feat, count, ws,
+                  stream=None) -> None:
+    check(lib().paam_features(cs.handle, seed & (2**64 - 1), pairs.data_ptr(),
+                              int(pairs.shape[0]), row_stride, feat.data_ptr(), count.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+          "paam_features")
+
+
+def paam_mlp_pack(params, packed, stream=None) -> None:
+    check(lib().paam_mlp_pack(params.data_ptr(), packed.data_ptr(), _stream_ptr(stream)),
+          "paam_mlp_pack")
+
+
+def paam_mlp_forward(params, packed, feat, count, n: int, row_stride: int, out, act=None,
+                     stream=None) -> None:
+    check(lib().paam_mlp_forward(params.data_ptr(), packed.data_ptr(), feat.data_ptr(),
+                                 count.data_ptr(), n, row_stride, out.data_ptr(), _dev_ptr(act),
+                                 _stream_ptr(stream)),
+          "paam_mlp_forward")
+
+
+def paam_mlp_backward_bytes(n: int) -> int:
+    return _size("paam_mlp_backward_bytes", n)
+
+
+def paam_mlp_backward(params, packed, feat, count, n: int, row_stride: int, out, target, act,
+                      grad, loss, ws, stream=None) -> None:
+    check(lib().paam_mlp_backward(params.data_ptr(), packed.data_ptr(), feat.data_ptr(),
+                                  count.data_ptr(), n, row_stride, out.data_ptr(),
+                                  target.data_ptr(), act.data_ptr(), grad.data_ptr(),
+                                  _dev_ptr(loss), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+          "paam_mlp_backward")
+
+
+def paam_mlp_adam_step(params, packed, m, v, grad, lr, beta1, beta2, eps, step,
+                       stream=None) -> None:
+    check(lib().paam_mlp_adam_step(params.data_ptr(), packed.data_ptr(), m.data_ptr(),
+                                   v.data_ptr(), grad.data_ptr(), lr, beta1, beta2, eps, step,
+                                   _stream_ptr(stream)),
+          "paam_mlp_adam_step")
+
+
+def paam_score_bytes(cs: Chainset, opts: paam_search_opts) -> int:
+    return _size("paam_score_bytes", cs.handle, ctypes.byref(opts))
+
+
+def paam_score_candidates(cs: Chainset, opts: paam_search_opts, params, packed, scores, ws,
+                          stream=None) -> None:
+    check(lib().paam_score_candidates(cs.handle, ctypes.byref(opts), params.data_ptr(),
+                                      packed.data_ptr(), scores.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), _stream_ptr(stream)),
+          "paam_score_candidates")
+
+
+def candidates(cs: Chainset, pairs, seed: int, stream=None, **wcrt_kw) -> dict:
+    """Exact analysis of explicit (set, k, util_permille) pairs; host results."""
+    import torch
+    pairs = torch.as_tensor(np.ascontiguousarray(pairs, np.int64)).to(cs.device)
+    o = wcrt_opts(**wcrt_kw)
+    n = int(pairs.shape[0])
+    out = CandOut(n, cs.device)
+    ws = workspace(paam_candidate_bytes(cs, o, n), cs.device)
+    paam_candidate_wcrt(cs, o, seed, pairs, out, ws, stream)
+    _sync(cs.device)
+    return {k: getattr(out, k).cpu().numpy()[:n] for k in ("sched", "worst_R", "worst_D", "ratio")}
+
+
+def features(cs: Chainset, pairs, seed: int, row_stride=None, stream=None) -> dict:
+    """Features of explicit pairs; host uint16 [n, row_stride, 48] and counts."""
+    import torch
+    pairs = torch.as_tensor(np.ascontiguousarray(pairs, np.int64)).to(cs.device)
+    n = int(pairs.shape[0])
+    rs = cs.max_chains if row_stride is None else row_stride
+    feat = torch.zeros(max(n, 1) * rs * N_FEAT, dtype=torch.int16, device=cs.device)
+    count = torch.empty(max(n, 1), dtype=torch.int32, device=cs.device)
+    ws = workspace(paam_features_bytes(cs, n), cs.device)
+    paam_features(cs, seed, pairs, rs, feat, count, ws, stream)
+    _sync(cs.device)
+    return {"feat": feat.cpu().numpy().view(np.uint16)[:n * rs * N_FEAT].reshape(n, rs, N_FEAT),
+            "count": count.cpu().numpy()[:n]}
+
+
+def _sync(device):
+    import torch
+    if str(device).startswith("cuda"):
+        torch.cuda.synchronize()
+
+
+class Network:
+    """Device state of the ranking network: float32 master parameters, the
+    packed bfloat16 weights and the Adam moments (all torch tensors)."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        import torch
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == MLP_PARAMS
+        self.device = device
+        self.params = torch.from_numpy(p.copy()).to(device)
+        self.packed = torch.zeros(MLP_PACKED, dtype=torch.int16, device=device)
+        self.m = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=device)
+        self.v = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=device)
+        self.step = 0
+        paam_mlp_pack(self.params, self.packed, stream)
+
+    def adam(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step += 1
+        paam_mlp_adam_step(self.params, self.packed, self.m, self.v, grad, lr, beta1, beta2, eps,
+                           self.step, stream)
+
+
+def score(cs: Chainset, net: Network, n_cand: int, seed: int, stream=None, **wcrt_kw):
+    """Network scores of every candidate of every set: device float32
+    [n_sets * n_cand]."""
+    import torch
+    o = search_opts(n_cand, seed, **wcrt_kw)
+    scores = torch.empty(max(cs.n_sets * n_cand, 1), dtype=torch.float32, device=cs.device)
+    ws = workspace(paam_score_bytes(cs, o), cs.device)
+    paam_score_candidates(cs, o, net.params, net.packed, scores, ws, stream)
+    return scores

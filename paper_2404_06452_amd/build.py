@@ -11,8 +11,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBPAAM = os.path.join(PKG, "libpaam.so")
 
-SOURCES = ["paam_host.cpp", "paam_kernels.hip"]
-HEADERS = [os.path.join(CSRC, "paam_internal.h"), os.path.join(INCLUDE, "paam.h")]
+SOURCES = ["paam_host.cpp", "paam_kernels.hip", "paam_surrogate.hip"]
+HEADERS = [os.path.join(CSRC, h) for h in ("paam_internal.h", "paam_device.h")] + [
+    os.path.join(INCLUDE, "paam.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

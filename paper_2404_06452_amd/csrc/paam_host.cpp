@@ -73,6 +73,7 @@ struct Plan {
   std::vector<int32_t> buckets;
   std::vector<int64_t> work_order;
   int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0;
+  int64_t max_tot = 0;
 };
 
 #define REQ(cond, ...)                                   \
@@ -113,7 +114,8 @@ paam_status parallel_ranges(int64_t n, F f) {
 }
 
 // Validates one set and returns its sub-chain count in *nrun.
-paam_status check_set(const paam_chainset_host *h, int64_t s, int *nrun, double *cost) {
+paam_status check_set(const paam_chainset_host *h, int64_t s, int *nrun, double *cost,
+                      int64_t *tot) {
   using paam::kTimeLimit;
   const int64_t c0 = h->set_chain_off[s];
   const int C = (int)(h->set_chain_off[s + 1] - c0);
@@ -131,6 +133,9 @@ paam_status check_set(const paam_chainset_host *h, int64_t s, int *nrun, double 
   for (int c = 1; c < C; ++c)
     REQ(pr[c] != pr[c - 1], "set %lld: duplicate chain priority", (long long)s);
   int runs = 0;
+  const int64_t a0 = h->set_accel_off[s];
+  int64_t total = 0;  // saturates at 2^62
+  auto add = [&](int64_t v) { total = total > ((int64_t)1 << 62) - v ? (int64_t)1 << 62 : total + v; };
   for (int c = 0; c < C; ++c) {
     const int64_t T = h->T[c0 + c], D = h->D[c0 + c];
     REQ(T > 0 && D > 0 && D <= T, "chain %lld: need 0 < D <= T (T=%lld D=%lld)",
@@ -147,7 +152,9 @@ paam_status check_set(const paam_chainset_host *h, int64_t s, int *nrun, double 
         RNG(h->A[g] < kTimeLimit, "segment %lld: A >= 2^36 ns", (long long)g);
         REQ(h->accel[g] >= 0 && h->accel[g] < NA, "segment %lld: accelerator out of range",
             (long long)g);
+        add(h->A[g] + 2 * h->accel_kappa[a0 + h->accel[g]] + h->accel_eps[a0 + h->accel[g]]);
       }
+      add(h->E[j]);
       if (e != prev_e) ++runs;
       prev_e = e;
     }
@@ -162,6 +169,7 @@ paam_status check_set(const paam_chainset_host *h, int64_t s, int *nrun, double 
       (long long)s);
   *nrun = runs;
   *cost = (double)runs * (double)(C + 4) + (double)nseg * (double)C;
+  *tot = total;
   return PAAM_OK;
 }
 
@@ -285,9 +293,10 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
   // pass 1: validate every set, count its sub-chains
   std::vector<int> nrun(S);
   std::vector<double> cost(S);
+  std::vector<int64_t> tot(S);
   paam_status st = parallel_ranges(S, [&](int64_t lo, int64_t hi) -> paam_status {
     for (int64_t s = lo; s < hi; ++s) {
-      paam_status r = check_set(h, s, &nrun[s], &cost[s]);
+      paam_status r = check_set(h, s, &nrun[s], &cost[s], &tot[s]);
       if (r != PAAM_OK) return r;
     }
     return PAAM_OK;
@@ -305,6 +314,7 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     P.max_X = std::max(P.max_X, (int32_t)(h->set_exec_off[s + 1] - h->set_exec_off[s]));
     P.max_NA = std::max(P.max_NA, (int32_t)(h->set_accel_off[s + 1] - h->set_accel_off[s]));
     P.max_runs = std::max(P.max_runs, nrun[s]);
+    P.max_tot = std::max(P.max_tot, tot[s]);
     P.max_segs = std::max(P.max_segs, (int32_t)(h->cb_seg_off[cb1] - h->cb_seg_off[cb0]));
   }
   P.n_runs = P.set_run_off[S];
@@ -524,6 +534,7 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   cs->arena_bytes = o.total;
   cs->n_exec = P.n_exec;
   cs->n_accel = P.n_accel;
+  cs->max_tot = P.max_tot;
   *out = cs;
   return PAAM_OK;
 }
@@ -656,6 +667,241 @@ paam_status paam_priority_search(const paam_chainset *cs, const paam_search_opts
     return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)", L.lds_bytes);
   int e = paam::launch_search(L, stream);
   if (e != 0) return hip_fail((hipError_t)e, "search launch");
+  return PAAM_OK;
+}
+
+// ------------------------------------------------------ surrogate entry points
+
+static int grid_items(int64_t n_items, int waves_per_cu) {
+  int64_t g = (int64_t)num_cus() * (waves_per_cu > 0 ? waves_per_cu : 8);
+  if (g > n_items) g = n_items;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+static bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+paam_status paam_candidate_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, int64_t n_pairs,
+                                 size_t *ws_bytes) {
+  if (!cs || !ws_bytes) return fail(PAAM_E_INVAL, "null argument");
+  paam_status st = check_opts(o);
+  if (st != PAAM_OK) return st;
+  if (n_pairs < 0) return fail(PAAM_E_INVAL, "n_pairs < 0");
+  *ws_bytes = 256 + (size_t)grid_items(n_pairs, o->waves_per_cu) * paam::wave_search_bytes(cs->dev);
+  return PAAM_OK;
+}
+
+paam_status paam_candidate_wcrt(const paam_chainset *cs, const paam_wcrt_opts *o, uint64_t seed,
+                                const int64_t *d_pairs, int64_t n_pairs, int8_t *sched,
+                                int64_t *worst_R, int64_t *worst_D, float *ratio, void *d_ws,
+                                size_t ws_bytes, paam_stream stream) {
+  size_t need = 0;
+  paam_status st = paam_candidate_bytes(cs, o, n_pairs, &need);
+  if (st != PAAM_OK) return st;
+  if (n_pairs > 0 && (!d_pairs || !sched || !worst_R || !worst_D))
+    return fail(PAAM_E_INVAL, "pairs and outputs must not be null");
+  if (!d_ws || ws_bytes < need)
+    return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  if (!aligned(d_ws, 256)) return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
+  paam::CandLaunch L;
+  L.b = cs->dev;
+  L.o = *o;
+  L.seed = seed;
+  L.pairs = d_pairs;
+  L.n_pairs = n_pairs;
+  L.sched = sched;
+  L.worst_R = worst_R;
+  L.worst_D = worst_D;
+  L.ratio = ratio;
+  L.counter = static_cast<unsigned long long *>(d_ws);
+  L.scratch = static_cast<unsigned char *>(d_ws) + 256;
+  L.scratch_stride = paam::wave_search_bytes(cs->dev);
+  L.analysis_stride = paam::wave_scratch_bytes(cs->dev);
+  L.lds_bytes = paam::wave_lds_bytes(cs->dev);
+  L.grid = grid_items(n_pairs, o->waves_per_cu);
+  if (L.lds_bytes > 160 * 1024)
+    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)", L.lds_bytes);
+  int e = paam::launch_candidates(L, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "candidate launch");
+  return PAAM_OK;
+}
+
+paam_status paam_features_bytes(const paam_chainset *cs, int64_t n_pairs, size_t *ws_bytes) {
+  if (!cs || !ws_bytes) return fail(PAAM_E_INVAL, "null argument");
+  if (n_pairs < 0) return fail(PAAM_E_INVAL, "n_pairs < 0");
+  *ws_bytes = 256 + (size_t)grid_items(n_pairs, 0) * paam::feat_wave_bytes(cs->dev);
+  return PAAM_OK;
+}
+
+paam_status paam_features(const paam_chainset *cs, uint64_t seed, const int64_t *d_pairs,
+                          int64_t n_pairs, int32_t row_stride, uint16_t *feat, int32_t *count,
+                          void *d_ws, size_t ws_bytes, paam_stream stream) {
+  size_t need = 0;
+  paam_status st = paam_features_bytes(cs, n_pairs, &need);
+  if (st != PAAM_OK) return st;
+  if (row_stride < cs->dev.max_C)
+    return fail(PAAM_E_INVAL, "row_stride %d below the largest set (%d chains)", row_stride,
+                cs->dev.max_C);
+  if (n_pairs > 0 && (!d_pairs || !feat || !count))
+    return fail(PAAM_E_INVAL, "pairs and outputs must not be null");
+  if (!aligned(feat, 16)) return fail(PAAM_E_INVAL, "feat is not 16-byte aligned");
+  if (cs->max_tot >= ((int64_t)1 << 40))
+    return fail(PAAM_E_RANGE, "a set's total demand reaches 2^40 ns");
+  if (!d_ws || ws_bytes < need)
+    return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  if (!aligned(d_ws, 256)) return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
+  paam::FeatLaunch L;
+  L.b = cs->dev;
+  L.seed = seed;
+  L.pairs = d_pairs;
+  L.n_items = n_pairs;
+  L.set0 = 0;
+  L.n_cand = 0;
+  L.util = 1000;
+  L.row_stride = row_stride;
+  L.feat = feat;
+  L.count = count;
+  L.counter = static_cast<unsigned long long *>(d_ws);
+  L.scratch = static_cast<unsigned char *>(d_ws) + 256;
+  L.scratch_stride = paam::feat_wave_bytes(cs->dev);
+  L.grid = grid_items(n_pairs, 0);
+  int e = paam::launch_features(L, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "features launch");
+  return PAAM_OK;
+}
+
+paam_status paam_mlp_pack(const float *d_params, uint16_t *d_packed, paam_stream stream) {
+  if (!d_params || !d_packed) return fail(PAAM_E_INVAL, "null argument");
+  int e = paam::launch_pack(d_params, d_packed, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "pack launch");
+  return PAAM_OK;
+}
+
+paam_status paam_mlp_forward(const float *d_params, const uint16_t *d_packed,
+                             const uint16_t *feat, const int32_t *count, int64_t n,
+                             int32_t row_stride, float *out, void *act, paam_stream stream) {
+  if (n < 0 || row_stride < 1) return fail(PAAM_E_INVAL, "n < 0 or row_stride < 1");
+  if (n > 0 && (!d_params || !d_packed || !feat || !count || !out))
+    return fail(PAAM_E_INVAL, "null argument");
+  if (!aligned(feat, 16) || !aligned(d_packed, 16) || (act && !aligned(act, 16)))
+    return fail(PAAM_E_INVAL, "feat, packed weights and act must be 16-byte aligned");
+  if (n > ((int64_t)1 << 35)) return fail(PAAM_E_RANGE, "too many candidates");
+  paam::FwdLaunch L{d_params, d_packed, feat, count, n, row_stride, out, act};
+  int e = paam::launch_forward(L, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "forward launch");
+  return PAAM_OK;
+}
+
+paam_status paam_mlp_backward_bytes(int64_t n, size_t *ws_bytes) {
+  if (!ws_bytes || n < 0) return fail(PAAM_E_INVAL, "bad argument");
+  *ws_bytes = 256 + (size_t)std::max<int64_t>(paam::backward_chunks(n), 1) *
+                        paam::backward_partial_stride() * sizeof(float);
+  return PAAM_OK;
+}
+
+paam_status paam_mlp_backward(const float *d_params, const uint16_t *d_packed,
+                              const uint16_t *feat, const int32_t *count, int64_t n,
+                              int32_t row_stride, const float *out, const float *target,
+                              const void *act, float *grad, float *loss, void *d_ws,
+                              size_t ws_bytes, paam_stream stream) {
+  size_t need = 0;
+  paam_status st = paam_mlp_backward_bytes(n, &need);
+  if (st != PAAM_OK) return st;
+  if (n < 1) return fail(PAAM_E_INVAL, "the loss needs n >= 1 candidates");
+  if (row_stride < 1) return fail(PAAM_E_INVAL, "row_stride < 1");
+  if (!d_params || !d_packed || !feat || !count || !out || !target || !act || !grad)
+    return fail(PAAM_E_INVAL, "null argument");
+  if (!d_ws || ws_bytes < need)
+    return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  if (!aligned(d_ws, 256)) return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
+  if (paam::backward_chunks(n) > 0x7FFFFFFF) return fail(PAAM_E_RANGE, "too many candidates");
+  paam::BwdLaunch L{d_params, d_packed, feat, count, n, row_stride, out, target, act,
+                    reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + 256),
+                    paam::backward_partial_stride()};
+  int e = paam::launch_backward(L, grad, loss, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "backward launch");
+  return PAAM_OK;
+}
+
+paam_status paam_mlp_adam_step(float *d_params, uint16_t *d_packed, float *d_m, float *d_v,
+                               const float *grad, float lr, float beta1, float beta2, float eps,
+                               int64_t step, paam_stream stream) {
+  if (!d_params || !d_packed || !d_m || !d_v || !grad) return fail(PAAM_E_INVAL, "null argument");
+  if (step < 1) return fail(PAAM_E_INVAL, "step counts from 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+    return fail(PAAM_E_INVAL, "need 0 <= beta < 1, eps > 0, lr >= 0");
+  int e = paam::launch_adam(d_params, d_packed, d_m, d_v, grad, lr, beta1, beta2, eps, step, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "adam launch");
+  return PAAM_OK;
+}
+
+// Candidates scored per chunk: at most 2^24 feature rows.
+static int64_t score_chunk_sets(const paam_chainset *cs, const paam_search_opts *o) {
+  const int64_t per = (int64_t)o->n_cand * std::max(cs->dev.max_C, 1);
+  int64_t n = ((int64_t)1 << 24) / per;
+  n = std::max<int64_t>(n, 1);
+  return std::min<int64_t>(n, std::max<int64_t>(cs->dev.n_sets, 1));
+}
+
+paam_status paam_score_bytes(const paam_chainset *cs, const paam_search_opts *o, size_t *ws_bytes) {
+  if (!cs || !o || !ws_bytes) return fail(PAAM_E_INVAL, "null argument");
+  if (o->n_cand < 1 || o->n_cand > 65536) return fail(PAAM_E_INVAL, "n_cand must be 1..65536");
+  paam_status st = check_opts(&o->wcrt);
+  if (st != PAAM_OK) return st;
+  const int64_t S = score_chunk_sets(cs, o);
+  const int64_t pairs = S * o->n_cand;
+  const int64_t items = S * ((o->n_cand + 63) / 64);
+  const size_t feat = ((size_t)pairs * std::max(cs->dev.max_C, 1) * 48 * 2 + 255) & ~(size_t)255;
+  const size_t cnt = ((size_t)pairs * 4 + 255) & ~(size_t)255;
+  *ws_bytes = 256 + feat + cnt + (size_t)grid_items(items, 0) * paam::feat_wave_bytes(cs->dev);
+  return PAAM_OK;
+}
+
+paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opts *o,
+                                  const float *d_params, const uint16_t *d_packed, float *scores,
+                                  void *d_ws, size_t ws_bytes, paam_stream stream) {
+  size_t need = 0;
+  paam_status st = paam_score_bytes(cs, o, &need);
+  if (st != PAAM_OK) return st;
+  if (!d_params || !d_packed || !scores) return fail(PAAM_E_INVAL, "null argument");
+  if (!d_ws || ws_bytes < need)
+    return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  if (!aligned(d_ws, 256) || !aligned(d_packed, 16))
+    return fail(PAAM_E_INVAL, "workspace (256 B) or packed weights (16 B) misaligned");
+  if (cs->max_tot >= ((int64_t)1 << 40) / std::max<int64_t>(1, (o->wcrt.util_permille + 999) / 1000))
+    return fail(PAAM_E_RANGE, "a set's total demand reaches 2^40 ns");
+  const int32_t Cm = std::max(cs->dev.max_C, 1);
+  const int64_t S = score_chunk_sets(cs, o);
+  const int64_t per = (o->n_cand + 63) / 64;
+  unsigned char *w = static_cast<unsigned char *>(d_ws);
+  const size_t feat_b = ((size_t)S * o->n_cand * Cm * 48 * 2 + 255) & ~(size_t)255;
+  const size_t cnt_b = ((size_t)S * o->n_cand * 4 + 255) & ~(size_t)255;
+  uint16_t *feat = reinterpret_cast<uint16_t *>(w + 256);
+  int32_t *count = reinterpret_cast<int32_t *>(w + 256 + feat_b);
+  unsigned char *scr = w + 256 + feat_b + cnt_b;
+  for (int64_t s0 = 0; s0 < cs->dev.n_sets; s0 += S) {
+    const int64_t ns = std::min<int64_t>(S, cs->dev.n_sets - s0);
+    paam::FeatLaunch F;
+    F.b = cs->dev;
+    F.seed = o->seed;
+    F.pairs = nullptr;
+    F.n_items = ns * per;
+    F.set0 = s0;
+    F.n_cand = o->n_cand;
+    F.util = o->wcrt.util_permille;
+    F.row_stride = Cm;
+    F.feat = feat;
+    F.count = count;
+    F.counter = reinterpret_cast<unsigned long long *>(w);
+    F.scratch = scr;
+    F.scratch_stride = paam::feat_wave_bytes(cs->dev);
+    F.grid = grid_items(F.n_items, 0);
+    int e = paam::launch_features(F, stream);
+    if (e != 0) return hip_fail((hipError_t)e, "features launch");
+    paam::FwdLaunch L{d_params, d_packed, feat, count, ns * o->n_cand, Cm,
+                      scores + s0 * (int64_t)o->n_cand, nullptr};
+    e = paam::launch_forward(L, stream);
+    if (e != 0) return hip_fail((hipError_t)e, "forward launch");
+  }
   return PAAM_OK;
 }
 

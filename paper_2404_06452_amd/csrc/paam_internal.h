@@ -70,6 +70,7 @@ struct paam_chainset {
   paam::DevBatch dev;
   size_t arena_bytes;
   int64_t n_exec, n_accel;
+  int64_t max_tot;  // largest total demand of a set: sum of E, A + 2 kappa and epsilon
 };
 
 namespace paam {
@@ -102,6 +103,75 @@ struct SearchLaunch {
   int grid;
 };
 
+struct CandLaunch {
+  DevBatch b;
+  paam_wcrt_opts o;
+  uint64_t seed;
+  const int64_t *pairs;         // [n_pairs][3] set, k, util_permille
+  int64_t n_pairs;
+  int8_t *sched;
+  int64_t *worst_R, *worst_D;
+  float *ratio;                 // or null
+  unsigned long long *counter;
+  unsigned char *scratch;
+  size_t scratch_stride;        // wave_search_bytes
+  size_t analysis_stride;       // offset of the candidate slot in a wave's scratch
+  size_t lds_bytes;
+  int grid;
+};
+
+// Features of candidate orders: explicit (set, k, util) pairs, or (pairs ==
+// null) every candidate of sets [set0, set0 + n_items / ceil(n_cand/64)) in
+// runs of 64 consecutive candidates.
+struct FeatLaunch {
+  DevBatch b;
+  uint64_t seed;
+  const int64_t *pairs;
+  int64_t n_items;
+  int64_t set0;
+  int32_t n_cand, util, row_stride;
+  uint16_t *feat;
+  int32_t *count;
+  unsigned long long *counter;
+  unsigned char *scratch;
+  size_t scratch_stride;
+  int grid;
+};
+
+struct FwdLaunch {
+  const float *params;
+  const uint16_t *packed;
+  const uint16_t *feat;
+  const int32_t *count;
+  int64_t n;
+  int32_t row_stride;
+  float *out;
+  void *act;
+};
+
+struct BwdLaunch {
+  const float *params;
+  const uint16_t *packed;
+  const uint16_t *feat;
+  const int32_t *count;
+  int64_t n;
+  int32_t row_stride;
+  const float *out, *target;
+  const void *act;
+  float *partial;
+  size_t part_stride;  // floats per chunk
+};
+
+size_t feat_wave_bytes(const DevBatch &b);
+size_t backward_partial_stride();
+int64_t backward_chunks(int64_t n);
+int launch_features(const FeatLaunch &L, void *stream);
+int launch_pack(const float *params, uint16_t *packed, void *stream);
+int launch_forward(const FwdLaunch &L, void *stream);
+int launch_backward(const BwdLaunch &L, float *grad, float *loss, void *stream);
+int launch_adam(float *P, uint16_t *Q, float *M, float *V, const float *G, float lr, float b1,
+                float b2, float eps, int64_t step, void *stream);
+
 // Scratch and LDS sizes for one wave analysing one set at a time.
 size_t wave_scratch_bytes(const DevBatch &b);
 size_t wave_lds_bytes(const DevBatch &b);
@@ -110,5 +180,6 @@ size_t wave_search_bytes(const DevBatch &b);
 // Launches (defined in paam_kernels.hip); return a hipError_t as int.
 int launch_wcrt(const WcrtLaunch &L, void *stream);
 int launch_search(const SearchLaunch &L, void *stream);
+int launch_candidates(const CandLaunch &L, void *stream);
 
 }  // namespace paam

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "paam_device.h"
 #include "paam_internal.h"
 
 namespace paam {
@@ -549,28 +550,24 @@ __global__ __launch_bounds__(kWave) void wcrt_kernel(WcrtLaunch L) {
 
 // ---------------------------- priority search ------------------------------
 
-// SplitMix64 [Steele, Lea & Flood 2014]: the output function, and output m of
-// the stream of a set, whose state starts at mix(seed + G*(set+1)) and
-// advances by G per output.
-__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-__device__ __forceinline__ uint64_t swap_stream(uint64_t seed, int64_t set, uint64_t m) {
-  const uint64_t G = 0x9E3779B97F4A7C15ull;
-  return splitmix_mix(splitmix_mix(seed + G * (uint64_t)(set + 1)) + G * (m + 1));
-}
-
 // Per-wave search state after the analysis scratch: the verdict slot, the
-// candidate order (chain at each rank) and the ranks of the chains.
+// candidate order (chain at each rank), the ranks of the chains, the selected
+// candidates of a guided search and the walk's step buffer.
+constexpr int kMaxTopK = 1024;
+
 struct SearchSlot {
   int64_t *worst_R;  // [1]
   int32_t *worst;    // [1]
   int8_t *sched;     // [1]
   int32_t *order;    // [max_C]
   int16_t *rank;     // [max_C]
+  int32_t *sel;      // [kMaxTopK]
+  int32_t *buf;      // [64]
 };
+
+__host__ __device__ inline size_t slot_sel_offset(int Cm) {
+  return (16 + 6 * (size_t)Cm + 15) & ~(size_t)15;
+}
 
 __device__ SearchSlot carve_slot(unsigned char *base, int Cm) {
   SearchSlot q;
@@ -579,15 +576,46 @@ __device__ SearchSlot carve_slot(unsigned char *base, int Cm) {
   q.sched = reinterpret_cast<int8_t *>(base + 12);
   q.order = reinterpret_cast<int32_t *>(base + 16);
   q.rank = reinterpret_cast<int16_t *>(base + 16 + 4 * (size_t)Cm);
+  q.sel = reinterpret_cast<int32_t *>(base + slot_sel_offset(Cm));
+  q.buf = q.sel + kMaxTopK;
   return q;
 }
 
-// Plain priority-order search.  Candidate 0 is the uploaded order; candidate
-// k >= 1 is candidate k-1 with the positions i = u1 mod C and
-// j = (i + 1 + u2 mod (C-1)) mod C swapped (u1, u2 = outputs 2k-2, 2k-1 of the
-// set's stream).  Each candidate is analysed by analyse_set in verdict mode,
-// reading the candidate's ranks through the batch's rank table; the first
-// feasible k is the smallest one.
+// The uploaded order of a set (candidate 0) into the slot.
+__device__ void base_order(const DevBatch &b, int64_t c0, int C, SearchSlot &q) {
+  for (int c = threadIdx.x; c < C; c += kWave) {
+    const int r = b.rank0[c0 + c];
+    q.order[r] = c;
+    q.rank[c] = (int16_t)r;
+  }
+  __syncthreads();
+}
+
+// Score key: ascending score in IEEE total order (-0 before +0, every NaN
+// last), ties to the lower candidate index.
+__device__ __forceinline__ uint64_t score_key(float f, int k) {
+  uint32_t u = __float_as_uint(f);
+  if (isnan(f)) {
+    u = 0xFFFFFFFFu;
+  } else {
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  }
+  return ((uint64_t)u << 32) | (uint32_t)k;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// Priority-order search.  Each candidate is analysed by analyse_set in verdict
+// mode, reading the candidate's ranks through the batch's rank table.
+// Plain: candidates 0, 1, ... in index order; the first feasible is the
+// smallest feasible k.  Guided: the top_k candidates by score in score order,
+// then (with fallback) the others in index order.
 __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
@@ -596,6 +624,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
   SearchSlot q = carve_slot(wbase + L.analysis_stride, L.b.max_C);
   paam_wcrt_opts o = L.o.wcrt;
   o.full = 0;
+  const int n_cand = L.o.n_cand;
   for (;;) {
     unsigned long long i = 0;
     if (threadIdx.x == 0) i = atomicAdd(L.counter, 1ull);
@@ -604,39 +633,81 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
     const int64_t set = L.b.work_order[i];
     const int64_t c0 = L.b.set_chain_off[set];
     const int C = (int)(L.b.set_chain_off[set + 1] - c0);
-    for (int c = threadIdx.x; c < C; c += kWave) {
-      const int r = L.b.rank0[c0 + c];
-      q.order[r] = c;
-      q.rank[c] = (int16_t)r;
-    }
-    __syncthreads();
+    base_order(L.b, c0, C, q);
     // the analysis reads rank0[c0 + c]: point it at this wave's candidate ranks
     DevBatch bq = L.b;
     bq.rank0 = q.rank - c0;
     int found = -1, n_eval = 0;
-    for (int k = 0; k < L.o.n_cand; ++k) {
-      if (k > 0 && C >= 2) {
-        if (threadIdx.x == 0) {
-          const uint64_t u1 = swap_stream(L.o.seed, set, 2 * (uint64_t)(k - 1));
-          const uint64_t u2 = swap_stream(L.o.seed, set, 2 * (uint64_t)(k - 1) + 1);
-          const int pa = (int)(u1 % (uint64_t)C);
-          const int pb = (int)((pa + 1 + (int64_t)(u2 % (uint64_t)(C - 1))) % C);
-          const int ca = q.order[pa], cb = q.order[pb];
-          q.order[pa] = cb;
-          q.order[pb] = ca;
-          q.rank[cb] = (int16_t)pa;
-          q.rank[ca] = (int16_t)pb;
+    int64_t cur = 0;  // candidate the slot's order holds
+    if (L.o.guided) {
+      const float *sc = L.o.d_scores + set * (int64_t)n_cand;
+      const int K = L.o.top_k < n_cand ? L.o.top_k : n_cand;
+      // the K smallest keys, in increasing order
+      uint64_t prev = 0;
+      for (int t = 0; t < K; ++t) {
+        uint64_t best = ~0ull;
+        for (int k = threadIdx.x; k < n_cand; k += kWave) {
+          const uint64_t key = score_key(sc[k], k);
+          if ((t == 0 || key > prev) && key < best) best = key;
         }
-        __syncthreads();
+        best = wave_min_u64(best);
+        if (threadIdx.x == 0) q.sel[t] = (int32_t)(uint32_t)best;
+        prev = best;
       }
-      analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
-      ++n_eval;
-      int v = 0;
-      if (threadIdx.x == 0) v = q.sched[0];  // written by lane 0 of analyse_set
-      v = __shfl(v, 0);
-      if (v != 0) {
-        found = v > 0 ? k : -2;
-        break;
+      __syncthreads();
+      for (int t = 0; t < K; ++t) {
+        const int k = q.sel[t];
+        if (k < cur) {
+          base_order(L.b, c0, C, q);
+          cur = 0;
+        }
+        walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
+        cur = k;
+        analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+        ++n_eval;
+        int v = 0;
+        if (threadIdx.x == 0) v = q.sched[0];  // written by lane 0 of analyse_set
+        v = __shfl(v, 0);
+        if (v != 0) {
+          found = v > 0 ? k : -2;
+          break;
+        }
+      }
+      if (found == -1 && L.o.fallback) {
+        for (int k = 0; k < n_cand; ++k) {
+          bool in = false;
+          for (int t = threadIdx.x; t < K; t += kWave) in |= q.sel[t] == k;
+          if (__any(in)) continue;
+          if (k < cur) {
+            base_order(L.b, c0, C, q);
+            cur = 0;
+          }
+          walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
+          cur = k;
+          analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+          ++n_eval;
+          int v = 0;
+          if (threadIdx.x == 0) v = q.sched[0];
+          v = __shfl(v, 0);
+          if (v != 0) {
+            found = v > 0 ? k : -2;
+            break;
+          }
+        }
+      }
+    } else {
+      for (int k = 0; k < n_cand; ++k) {
+        walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
+        cur = k;
+        analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+        ++n_eval;
+        int v = 0;
+        if (threadIdx.x == 0) v = q.sched[0];
+        v = __shfl(v, 0);
+        if (v != 0) {
+          found = v > 0 ? k : -2;
+          break;
+        }
       }
     }
     if (threadIdx.x == 0) {
@@ -645,6 +716,56 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
     }
     if (L.found_prio && found >= 0)
       for (int r = threadIdx.x; r < C; r += kWave) L.found_prio[c0 + q.order[r]] = C - r;
+    __syncthreads();
+  }
+}
+
+// Exact analysis of explicit (set, k, util_permille) candidates: every
+// chain's bound at cap_mult * D, reduced to the worst chain and its ratio.
+__global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
+  unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
+  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs);
+  SearchSlot q = carve_slot(wbase + L.analysis_stride, L.b.max_C);
+  // Grid-stride over the pairs: the item index derives from blockIdx only, so
+  // it is wave-uniform by construction.  (With a lane-0 queue fetch, the path
+  // that skips a malformed pair was split by the compiler into a loop that
+  // lanes 1..63 never leave.)
+  for (int64_t i = blockIdx.x; i < L.n_pairs; i += gridDim.x) {
+    const int64_t set = L.pairs[3 * i], k = L.pairs[3 * i + 1], u = L.pairs[3 * i + 2];
+    if (set < 0 || set >= L.b.n_sets || k < 0 || k > 0x7FFFFFFF || u < 0 || u > 0x7FFFFFFF) {
+      if (threadIdx.x == 0) {
+        L.sched[i] = -2;
+        L.worst_R[i] = PAAM_INF;
+        L.worst_D[i] = 0;
+        if (L.ratio) L.ratio[i] = (float)L.o.cap_mult;
+      }
+      continue;
+    }
+    const int64_t c0 = L.b.set_chain_off[set];
+    const int C = (int)(L.b.set_chain_off[set + 1] - c0);
+    base_order(L.b, c0, C, q);
+    walk_order(q.order, q.rank, C, L.seed, set, 0, k, q.buf);
+    DevBatch bq = L.b;
+    bq.rank0 = q.rank - c0;
+    paam_wcrt_opts o = L.o;
+    o.full = 1;
+    o.util_permille = (int32_t)u;
+    analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+    if (threadIdx.x == 0) {
+      const int w = q.worst[0];
+      const int64_t wR = q.worst_R[0];
+      const int64_t D = L.b.D[c0 + (w < 0 ? 0 : w)];
+      L.sched[i] = q.sched[0];
+      L.worst_R[i] = wR;
+      L.worst_D[i] = D;
+      if (L.ratio) {
+        const double cap = (double)L.o.cap_mult;
+        double r = wR == PAAM_INF ? cap : (double)wR / (double)D;
+        L.ratio[i] = (float)(r < cap ? r : cap);
+      }
+    }
     __syncthreads();
   }
 }
@@ -658,7 +779,8 @@ size_t wave_scratch_bytes(const DevBatch &b) {
 }
 
 size_t wave_search_bytes(const DevBatch &b) {
-  return wave_scratch_bytes(b) + ((16 + 6 * (size_t)b.max_C + 255) & ~(size_t)255);
+  const size_t slot = slot_sel_offset(b.max_C) + 4 * (size_t)(kMaxTopK + 64);
+  return wave_scratch_bytes(b) + ((slot + 255) & ~(size_t)255);
 }
 
 size_t wave_lds_bytes(const DevBatch &b) {
@@ -673,6 +795,13 @@ int launch_wcrt(const WcrtLaunch &L, void *stream) {
   if (e != hipSuccess) return (int)e;
   if (L.b.n_sets == 0) return 0;
   hipLaunchKernelGGL(wcrt_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  return (int)hipGetLastError();
+}
+
+int launch_candidates(const CandLaunch &L, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (L.n_pairs == 0) return 0;
+  hipLaunchKernelGGL(candidate_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
 }
 

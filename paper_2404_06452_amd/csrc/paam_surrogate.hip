@@ -1,0 +1,715 @@
+// HIP kernels of the candidate-ranking surrogate for gfx950: per-chain
+// features of candidate priority orders, the network's forward pass on the
+// matrix cores (bfloat16 operands, float32 accumulation), its backward pass
+// and Adam in float32.  The exact analysis stays the judge of schedulability;
+// these kernels only rank candidates for it.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "paam_device.h"
+#include "paam_internal.h"
+
+namespace paam {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ features
+
+// Per-wave tables of one set, independent of the priority order.
+struct FeatTables {
+  int64_t *Ec, *Acc, *epc, *Emax, *qsum, *qasum;  // [Cm]
+  int32_t *S, *dl, *ncb, *mine, *uses;             // [Cm]
+  int64_t *Ece, *Acce, *epce, *bl, *bS, *q, *qa;  // [Cm][Xm]
+  int32_t *runs;                                   // [Cm][Xm]
+  int64_t *Ahat, *Amax, *qA;                       // [Cm][NAm]
+  int32_t *dca, *nra, *level;                      // [Cm][NAm]
+  int32_t *order, *buf;                            // [Cm], [64]
+  int16_t *rank;                                   // [Cm]
+};
+
+__host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
+  const size_t C = Cm, CX = (size_t)Cm * Xm, CA = (size_t)Cm * NAm;
+  return 8 * (6 * C + 7 * CX + 3 * CA) + 4 * (5 * C + CX + 3 * CA + C + 64) + 2 * C + 64;
+}
+
+__device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
+  FeatTables t;
+  const size_t C = Cm, CX = (size_t)Cm * Xm, CA = (size_t)Cm * NAm;
+  int64_t *d = reinterpret_cast<int64_t *>(base);
+  t.Ec = d; d += C;
+  t.Acc = d; d += C;
+  t.epc = d; d += C;
+  t.Emax = d; d += C;
+  t.qsum = d; d += C;
+  t.qasum = d; d += C;
+  t.Ece = d; d += CX;
+  t.Acce = d; d += CX;
+  t.epce = d; d += CX;
+  t.bl = d; d += CX;
+  t.bS = d; d += CX;
+  t.q = d; d += CX;
+  t.qa = d; d += CX;
+  t.Ahat = d; d += CA;
+  t.Amax = d; d += CA;
+  t.qA = d; d += CA;
+  int32_t *i = reinterpret_cast<int32_t *>(d);
+  t.S = i; i += C;
+  t.dl = i; i += C;
+  t.ncb = i; i += C;
+  t.mine = i; i += C;
+  t.uses = i; i += C;
+  t.runs = i; i += CX;
+  t.dca = i; i += CA;
+  t.nra = i; i += CA;
+  t.level = i; i += CA;
+  t.order = i; i += C;
+  t.buf = i; i += 64;
+  t.rank = reinterpret_cast<int16_t *>(i);
+  return t;
+}
+
+__device__ __forceinline__ int64_t scale_E(int64_t x, int32_t u) {
+  return u == 1000 ? x : (x * (int64_t)u) / 1000;
+}
+
+// (double)n / (double)m, 0 when m == 0.
+__device__ __forceinline__ double fratio(int64_t n, int64_t m) {
+  return m == 0 ? 0.0 : (double)n / (double)m;
+}
+
+constexpr int64_t kQ = 65536;  // fixed-point scale of utilisation terms
+
+// Order-independent tables of a set at utilisation scale u.  Lane c owns the
+// rows of chain c.  Ends synchronised.
+__device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables &t) {
+  const int64_t c0 = b.set_chain_off[set];
+  const int C = (int)(b.set_chain_off[set + 1] - c0);
+  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
+  const int64_t a0 = b.set_accel_off[set];
+  const int NA = (int)(b.set_accel_off[set + 1] - a0);
+  const int NAm = NA > 0 ? NA : 1;
+  const int64_t cb0 = b.set_cb_off[set];
+  const int64_t run0 = b.set_run_off[set];
+  const int nrun = (int)(b.set_run_off[set + 1] - run0);
+  for (int c = threadIdx.x; c < C; c += kWave) {
+    int64_t E = 0, Ac = 0, ep = 0, Emax = 0;
+    int S = 0, dl = 0, ncb = 0;
+    uint32_t mine = 0, uses = 0;
+    for (int e = 0; e < X; ++e) {
+      const int i = c * X + e;
+      t.Ece[i] = t.Acce[i] = t.epce[i] = t.bl[i] = t.bS[i] = 0;
+      t.runs[i] = 0;
+    }
+    for (int a = 0; a < NAm; ++a) {
+      const int i = c * NAm + a;
+      t.Ahat[i] = t.Amax[i] = 0;
+      t.dca[i] = t.nra[i] = 0;
+    }
+    for (int s = 0; s < nrun; ++s) {
+      if (b.run_chain[run0 + s] != c) continue;
+      const int e = b.run_exec[run0 + s];
+      const int ie = c * X + e;
+      ++S;
+      t.runs[ie] += 1;
+      mine |= 1u << e;
+      uint32_t accs = 0;
+      for (int j = b.run_cb_lo[run0 + s]; j < b.run_cb_hi[run0 + s]; ++j) {
+        const int64_t Ej = scale_E(b.E[cb0 + j], u);
+        ++ncb;
+        E += Ej;
+        t.Ece[ie] += Ej;
+        Emax = Ej > Emax ? Ej : Emax;
+        t.bl[ie] = Ej > t.bl[ie] ? Ej : t.bl[ie];
+        int64_t bj = Ej;
+        for (int64_t g = b.cb_seg_off[cb0 + j]; g < b.cb_seg_off[cb0 + j + 1]; ++g) {
+          const int a = b.seg_accel[g];
+          const int64_t As = scale_E(b.A[g], u) + 2 * b.akappa[a0 + a];
+          const int64_t ea = b.aeps[a0 + a];
+          Ac += As;
+          ep += ea;
+          ++dl;
+          t.Acce[ie] += As;
+          t.epce[ie] += ea;
+          const int ia = c * NAm + a;
+          t.Ahat[ia] += As;
+          t.dca[ia] += 1;
+          t.Amax[ia] = As > t.Amax[ia] ? As : t.Amax[ia];
+          bj += As + ea;
+          accs |= 1u << a;
+          uses |= 1u << a;
+        }
+        t.bS[ie] = bj > t.bS[ie] ? bj : t.bS[ie];
+      }
+      for (uint32_t m = accs; m; m &= m - 1) t.nra[c * NAm + (__ffs(m) - 1)] += 1;
+    }
+    const int64_t T = b.T[c0 + c];
+    int64_t qs = 0, qas = 0;
+    for (int e = 0; e < X; ++e) {
+      const int i = c * X + e;
+      t.q[i] = (t.Ece[i] * kQ) / T;
+      t.qa[i] = ((t.Acce[i] + t.epce[i]) * kQ) / T;
+      qs += t.q[i];
+      qas += t.qa[i];
+    }
+    for (int a = 0; a < NAm; ++a) t.qA[c * NAm + a] = (t.Ahat[c * NAm + a] * kQ) / T;
+    t.Ec[c] = E;
+    t.Acc[c] = Ac;
+    t.epc[c] = ep;
+    t.Emax[c] = Emax;
+    t.qsum[c] = qs;
+    t.qasum[c] = qas;
+    t.S[c] = S;
+    t.dl[c] = dl;
+    t.ncb[c] = ncb;
+    t.mine[c] = (int32_t)mine;
+    t.uses[c] = (int32_t)uses;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void put_feat(uint16_t *row, int f, double v) {
+  row[f] = bf16_rne((float)v);
+}
+
+// The 48 features of every chain of a set under the order in t.order/t.rank,
+// written to rows out[c * 48 ...].  Feature k here is feature k of the
+// documented list; each is (double)N / (double)M of exact integers.  Returns
+// false (and writes nothing) when the set's total demand reaches 2^40, where
+// the integer numerators could overflow.
+__device__ bool feat_candidate(const DevBatch &b, int64_t set, FeatTables &t, uint16_t *out) {
+  const int64_t c0 = b.set_chain_off[set];
+  const int C = (int)(b.set_chain_off[set + 1] - c0);
+  const int64_t x0 = b.set_exec_off[set];
+  const int X = (int)(b.set_exec_off[set + 1] - x0);
+  const int64_t a0 = b.set_accel_off[set];
+  const int NA = (int)(b.set_accel_off[set + 1] - a0);
+  const int NAm = NA > 0 ? NA : 1;
+  const int64_t hop = b.eps_hop[set];
+  // bucket level of every (chain, accelerator) under this order (Sec. IV-C)
+  for (int c = threadIdx.x; c < C; c += kWave) {
+    const int rho = t.rank[c];
+    for (int a = 0; a < NA; ++a) {
+      int lev = -1;
+      if (t.dca[c * NAm + a] > 0) {
+        int r = 0, m = 0;
+        for (int h = 0; h < C; ++h) {
+          if (t.dca[h * NAm + a] > 0) {
+            ++m;
+            if (t.rank[h] < rho) ++r;
+          }
+        }
+        lev = (int)(((int64_t)r * b.buckets[a0 + a]) / m);
+      }
+      t.level[c * NAm + a] = lev;
+    }
+  }
+  __syncthreads();
+  // set-level sums (identical on every lane)
+  int64_t sum_q = 0, sum_qA = 0, sum_dem = 0, Tmin = INT64_MAX, max_qe = 0, tot = 0;
+  for (int h = 0; h < C; ++h) {
+    tot += t.Ec[h] + t.Acc[h] + t.epc[h];
+    sum_q += t.qsum[h];
+    for (int a = 0; a < NA; ++a) sum_qA += t.qA[h * NAm + a];
+    sum_dem += t.Ec[h] + t.Acc[h];
+    const int64_t Th = b.T[c0 + h];
+    Tmin = Th < Tmin ? Th : Tmin;
+  }
+  if (tot >= ((int64_t)1 << 40)) return false;
+  for (int e = 0; e < X; ++e) {
+    int64_t s = 0;
+    for (int h = 0; h < C; ++h) s += t.q[h * X + e];
+    max_qe = s > max_qe ? s : max_qe;
+  }
+  for (int c = threadIdx.x; c < C; c += kWave) {
+    uint16_t *row = out + (size_t)c * 48;
+    const int rho = t.rank[c];
+    const int64_t T = b.T[c0 + c], D = b.D[c0 + c];
+    const int spin_c = b.spin[c0 + c];
+    const int S = t.S[c];
+    const int64_t own = t.Ec[c] + t.Acc[c] + t.epc[c] + (int64_t)(S - 1) * hop;
+    const uint32_t mine = (uint32_t)t.mine[c], uses = (uint32_t)t.uses[c];
+    put_feat(row, 0, fratio(t.Ec[c], D));
+    put_feat(row, 1, fratio(t.Acc[c], D));
+    put_feat(row, 2, fratio(t.epc[c], D));
+    put_feat(row, 3, fratio((int64_t)(S - 1) * hop, D));
+    put_feat(row, 4, fratio(own, D));
+    put_feat(row, 5, fratio(t.Emax[c], D));
+    put_feat(row, 6, fratio(S, 16));
+    put_feat(row, 7, fratio(t.dl[c], 16));
+    put_feat(row, 8, fratio(t.ncb[c], 32));
+    put_feat(row, 9, fratio(__popc(mine), X));
+    put_feat(row, 10, fratio(D, T));
+    put_feat(row, 11, fratio(T, (int64_t)1 << 30));
+    put_feat(row, 12, spin_c ? 1.0 : 0.0);
+    put_feat(row, 13, fratio(t.qsum[c], kQ));
+    put_feat(row, 14, fratio(t.qasum[c], kQ));
+    put_feat(row, 15, fratio(rho, C));
+    put_feat(row, 16, fratio(C - 1 - rho, C));
+    put_feat(row, 17, rho == 0 ? 1.0 : 0.0);
+    put_feat(row, 18, rho == C - 1 ? 1.0 : 0.0);
+    int n19 = 0, n20 = 0;
+    for (int h = 0; h < C; ++h) {
+      const int64_t Th = b.T[c0 + h];
+      if (t.rank[h] < rho && Th > T) ++n19;
+      if (t.rank[h] > rho && Th < T) ++n20;
+    }
+    put_feat(row, 19, fratio(n19, C));
+    put_feat(row, 20, fratio(n20, C));
+    // hp on the chain's executors, blocking, hpp
+    int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0, n_hpp = 0,
+            q_hpp = 0;
+    int n25 = 0, n29 = 0;
+    for (int e = 0; e < X; ++e) {
+      const int64_t rce = t.runs[c * X + e];
+      int64_t sq = 0, sqa = 0, scar = 0, mbl = 0, mbs = 0;
+      int nhp = 0, nlp = 0;
+      for (int h = 0; h < C; ++h) {
+        const int ih = h * X + e;
+        if (t.rank[h] < rho) {
+          sq += t.q[ih];
+          sqa += t.qa[ih];
+          scar += t.Ece[ih] + t.Acce[ih] + t.epce[ih];
+          nhp += t.runs[ih] > 0;
+        } else if (t.rank[h] > rho) {
+          mbl = t.bl[ih] > mbl ? t.bl[ih] : mbl;
+          mbs = t.bS[ih] > mbs ? t.bS[ih] : mbs;
+          nlp += t.runs[ih] > 0;
+        }
+      }
+      n_carry += rce * 2 * scar;
+      n_bp += rce * mbl;
+      n_bs += rce * mbs;
+      if (rce > 0) {
+        q21 += sq;
+        q22 += sqa;
+        q24 = sq + sqa > q24 ? sq + sqa : q24;
+        n25 += nhp;
+        n29 += nlp;
+        m28 = mbs > m28 ? mbs : m28;
+      }
+      for (uint32_t m = b.hpx_mask[x0 + e]; m; m &= m - 1) {
+        const int e2 = __ffs(m) - 1;
+        for (int h = 0; h < C; ++h) {
+          if (h == c) continue;
+          const int ih = h * X + e2;
+          const bool sp = b.spin[c0 + h] != 0;
+          const int64_t w = t.Ece[ih] + (sp ? t.Acce[ih] + t.epce[ih] : t.epce[ih]);
+          n_hpp += rce * 2 * w;
+          if (rce > 0) q_hpp += t.q[ih] + (sp ? t.qa[ih] : 0);
+        }
+      }
+    }
+    put_feat(row, 21, fratio(q21, kQ));
+    put_feat(row, 22, fratio(q22, kQ));
+    put_feat(row, 23, fratio(n_carry, D));
+    put_feat(row, 24, fratio(q24, kQ));
+    put_feat(row, 25, fratio(n25, C));
+    put_feat(row, 26, fratio(n_bp, D));
+    put_feat(row, 27, fratio(n_bs, D));
+    put_feat(row, 28, fratio(m28, D));
+    put_feat(row, 29, fratio(n29, C));
+    put_feat(row, 30, fratio(n_hpp, D));
+    put_feat(row, 31, fratio(q_hpp, kQ));
+    // accelerators
+    int64_t n_acc = 0, q33 = 0, n_bacc = 0;
+    int n36 = 0, f37 = 0;
+    double f35 = 0.0;
+    for (int a = 0; a < NA; ++a) {
+      if (!((uses >> a) & 1u)) continue;
+      const int lev = t.level[c * NAm + a];
+      int64_t hpA = 0, bacc = 0;
+      for (int h = 0; h < C; ++h) {
+        const int ih = h * NAm + a;
+        if (t.rank[h] < rho) {
+          hpA += t.Ahat[ih];
+          q33 += t.qA[ih];
+          n36 += t.dca[ih] > 0;
+          f37 |= t.Ahat[ih] > 0;
+        } else if (t.rank[h] > rho && t.dca[ih] > 0 && t.level[ih] == lev) {
+          bacc = t.Amax[ih] > bacc ? t.Amax[ih] : bacc;
+        }
+      }
+      n_acc += 2 * (int64_t)t.nra[c * NAm + a] * hpA;
+      n_bacc += (int64_t)t.dca[c * NAm + a] * bacc;
+      const double lv = fratio(lev, b.buckets[a0 + a]);
+      f35 = lv > f35 ? lv : f35;
+    }
+    put_feat(row, 32, fratio(n_acc, D));
+    put_feat(row, 33, fratio(q33, kQ));
+    put_feat(row, 34, fratio(n_bacc, D));
+    put_feat(row, 35, f35);
+    put_feat(row, 36, fratio(n36, C));
+    put_feat(row, 37, f37 ? 1.0 : 0.0);
+    put_feat(row, 38, fratio(sum_q, (int64_t)X * kQ));
+    put_feat(row, 39, fratio(max_qe, kQ));
+    put_feat(row, 40, fratio(sum_qA, kQ));
+    put_feat(row, 41, fratio(C, 256));
+    put_feat(row, 42, fratio(X, 8));
+    put_feat(row, 43, fratio(NA, 8));
+    put_feat(row, 44, fratio(Tmin, T));
+    const int64_t n_est = own + n_carry + n_bs + n_hpp + n_acc + n_bacc;
+    const int64_t q_est = q21 + q22 + q_hpp + q33;
+    put_feat(row, 45, fratio(n_est, D));
+    put_feat(row, 46, fratio(n_est, D) + fratio(q_est, kQ));
+    put_feat(row, 47, fratio(t.Ec[c] + t.Acc[c], sum_dem));
+  }
+  return true;
+}
+
+// Work item i: explicit pairs (one candidate each), or in range mode a run of
+// up to 64 consecutive candidates of one set.
+__global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
+  unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
+  const int NAm = L.b.max_NA > 0 ? L.b.max_NA : 1;
+  FeatTables t = carve_feat(wbase, L.b.max_C, L.b.max_X, NAm);
+  // grid-stride: the item index is wave-uniform by construction
+  for (int64_t i = blockIdx.x; i < L.n_items; i += gridDim.x) {
+    int64_t set, k0, n_k, out0;
+    int32_t u;
+    if (L.pairs) {
+      set = L.pairs[3 * i];
+      k0 = L.pairs[3 * i + 1];
+      const int64_t uu = L.pairs[3 * i + 2];
+      n_k = 1;
+      out0 = (int64_t)i;
+      if (set < 0 || set >= L.b.n_sets || k0 < 0 || k0 > 0x7FFFFFFF || uu < 0 ||
+          uu > 0x7FFFFFFF) {
+        if (threadIdx.x == 0) L.count[i] = -1;
+        continue;
+      }
+      u = (int32_t)uu;
+    } else {
+      const int64_t per = (L.n_cand + 63) / 64;
+      set = L.set0 + (int64_t)i / per;
+      k0 = ((int64_t)i % per) * 64;
+      n_k = L.n_cand - k0 < 64 ? L.n_cand - k0 : 64;
+      out0 = (set - L.set0) * L.n_cand + k0;
+      u = L.util;
+    }
+    const int64_t c0 = L.b.set_chain_off[set];
+    const int C = (int)(L.b.set_chain_off[set + 1] - c0);
+    feat_build(L.b, set, u, t);
+    for (int c = threadIdx.x; c < C; c += kWave) {
+      const int r = L.b.rank0[c0 + c];
+      t.order[r] = c;
+      t.rank[c] = (int16_t)r;
+    }
+    __syncthreads();
+    int64_t cur = 0;
+    for (int64_t k = k0; k < k0 + n_k; ++k) {
+      walk_order(t.order, t.rank, C, L.seed, set, cur, k, t.buf);
+      cur = k;
+      const int64_t o = out0 + (k - k0);
+      const bool ok = feat_candidate(L.b, set, t, L.feat + (size_t)o * L.row_stride * 48);
+      if (threadIdx.x == 0) L.count[o] = ok ? C : -2;
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ network
+
+constexpr int NF = 48, NH = 256, KP = 64;
+constexpr int OW1 = 0, OB1 = 12288, OW2 = 12544, OB2 = 78080, OW3 = 78336, OB3 = 78592;
+constexpr int NPARAM = 78593;
+constexpr int PW1 = 0, PW2 = NH * KP, PW3 = PW2 + NH * NH, NPACK = PW3 + NH;
+
+// Packed bfloat16 copy of the weights (W1 padded to 64 columns).
+__global__ void pack_kernel(const float *__restrict__ P, uint16_t *__restrict__ Q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NPACK) return;
+  float v = 0.0f;
+  if (i < PW2) {
+    const int j = i / KP, f = i % KP;
+    v = f < NF ? P[OW1 + j * NF + f] : 0.0f;
+  } else if (i < PW3) {
+    v = P[OW2 + (i - PW2)];
+  } else {
+    v = P[OW3 + (i - PW3)];
+  }
+  Q[i] = bf16_rne(v);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+  const uint4 v = make_uint4(0, 0, 0, 0);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+// 8 features k0..k0+7 of a row (zero past the 48 features or past the rows);
+// rows are 96 bytes apart, so 16-byte aligned when the buffer is.
+__device__ __forceinline__ bf16x8 load_x8(const uint16_t *row, int k0, bool valid) {
+  if (!valid || k0 >= NF) return zero8();
+  return load8(row + k0);
+}
+
+// One wave: 16 candidates (rows of layer 2).  Layer 1 runs per candidate in
+// 16-row tiles on the matrix cores (v_mfma_f32_16x16x32_bf16: lane l holds
+// A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16], D[4(l/16)+j][l%16]); the ReLU
+// outputs of the valid rows are summed per column into the pool.
+__global__ __launch_bounds__(kWave) void forward_kernel(FwdLaunch L) {
+  __shared__ uint16_t Pq[16][NH + 8];   // pooled vectors (bfloat16) of the 16 candidates
+  const int l = threadIdx.x;
+  const int li = l & 15, lg = l >> 4;
+  const int64_t base = (int64_t)blockIdx.x * 16;
+  const uint16_t *W1 = L.packed + PW1, *W2 = L.packed + PW2, *w3 = L.packed + PW3;
+  const float *b1 = L.params + OB1, *b2 = L.params + OB2;
+  for (int m = 0; m < 16; ++m) {
+    const int64_t cand = base + m;
+    float pool[16];
+    for (int nt = 0; nt < 16; ++nt) pool[nt] = 0.0f;
+    int rows = 0;
+    if (cand < L.n) rows = L.count[cand];
+    if (rows < 0) rows = 0;
+    const uint16_t *X = L.feat + (size_t)cand * L.row_stride * NF;
+    for (int r0 = 0; r0 < rows; r0 += 16) {
+      const int r = r0 + li;
+      const bool rv = r < rows;
+      const bf16x8 a0 = load_x8(X + (size_t)r * NF, 8 * lg, rv);
+      const bf16x8 a1 = load_x8(X + (size_t)r * NF, 32 + 8 * lg, rv);
+      for (int nt = 0; nt < 16; ++nt) {
+        const int n = nt * 16 + li;
+        const bf16x8 bb0 = load8(W1 + (size_t)n * KP + 8 * lg);
+        const bf16x8 bb1 = load8(W1 + (size_t)n * KP + 32 + 8 * lg);
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
+        const float bias = b1[n];
+        float s = 0.0f;
+        for (int j = 0; j < 4; ++j) {
+          const int rr = r0 + 4 * lg + j;
+          const float z = acc[j] + bias;
+          s += (rr < rows && z > 0.0f) ? z : 0.0f;
+        }
+        pool[nt] += s;
+      }
+    }
+    // column sums across the four row groups, then the mean
+    for (int nt = 0; nt < 16; ++nt) {
+      float s = pool[nt];
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      const float p = rows > 0 ? s / (float)rows : 0.0f;
+      if (lg == 0) Pq[m][nt * 16 + li] = bf16_rne(p);
+    }
+  }
+  __syncthreads();
+  // layer 2 on the 16 pooled vectors: A = Pq (16 x 256), B = W2^T
+  float ypart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int nt = 0; nt < 16; ++nt) {
+    const int n = nt * 16 + li;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kk = 0; kk < NH; kk += 32) {
+      const bf16x8 a = load8(&Pq[li][kk + 8 * lg]);
+      const bf16x8 bb = load8(W2 + (size_t)n * NH + kk + 8 * lg);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+    }
+    const float bias = b2[n];
+    const float w = bf16_value(w3[n]);
+    for (int j = 0; j < 4; ++j) {
+      const int m = 4 * lg + j;
+      const float z = acc[j] + bias;
+      const uint16_t hq = bf16_rne(z > 0.0f ? z : 0.0f);
+      ypart[j] += w * bf16_value(hq);
+      if (L.act && base + m < L.n) {
+        uint16_t *a = reinterpret_cast<uint16_t *>(L.act) + (size_t)(base + m) * 512;
+        a[256 + n] = hq;
+      }
+    }
+  }
+  // y of candidate 4*lg + j: sum over the 16 lanes of the row group
+  for (int j = 0; j < 4; ++j) {
+    float s = ypart[j];
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    s += __shfl_xor(s, 8);
+    const int64_t cand = base + 4 * lg + j;
+    if (li == 0 && cand < L.n) L.out[cand] = s + L.params[OB3];
+  }
+  if (L.act) {
+    for (int m = 0; m < 16; ++m) {
+      const int64_t cand = base + m;
+      if (cand >= L.n) break;
+      uint16_t *a = reinterpret_cast<uint16_t *>(L.act) + (size_t)cand * 512;
+      for (int k = l; k < NH; k += kWave) a[k] = Pq[m][k];
+    }
+  }
+}
+
+// Backward over a chunk of kBwdChunk candidates per workgroup of 256 threads
+// (thread j = hidden unit j); writes this chunk's partial gradient.
+constexpr int kBwdChunk = 16;
+
+__global__ __launch_bounds__(256) void backward_kernel(BwdLaunch L) {
+  __shared__ float dz2[kBwdChunk][NH];
+  __shared__ float pq[kBwdChunk][NH];
+  __shared__ float dp[kBwdChunk][NH];
+  __shared__ float xs[NF];
+  const int j = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * kBwdChunk;
+  const int nc = (int)((L.n - c0) < kBwdChunk ? (L.n - c0) : kBwdChunk);
+  float *part = L.partial + (size_t)blockIdx.x * L.part_stride;
+  const uint16_t *W2 = L.packed + PW2, *W1 = L.packed + PW1;
+  const float w3j = bf16_value(L.packed[PW3 + j]);
+  const float inv_n = 1.0f / (float)L.n;
+  float gw3 = 0.0f, gb2 = 0.0f, gb3 = 0.0f, lsum = 0.0f;
+  for (int m = 0; m < nc; ++m) {
+    const int64_t cand = c0 + m;
+    const uint16_t *a = reinterpret_cast<const uint16_t *>(L.act) + (size_t)cand * 512;
+    const float d = L.out[cand] - L.target[cand];
+    const float dy = 2.0f * d * inv_n;
+    const float h2 = bf16_value(a[256 + j]);
+    const float g = h2 > 0.0f ? dy * w3j : 0.0f;
+    dz2[m][j] = g;
+    pq[m][j] = bf16_value(a[j]);
+    gw3 += dy * h2;
+    gb2 += g;
+    if (j == 0) {
+      gb3 += dy;
+      lsum += d * d;
+    }
+  }
+  __syncthreads();
+  // dW2[j][k] = sum_m dz2[m][j] * pq[m][k]
+  for (int k = 0; k < NH; ++k) {
+    float s = 0.0f;
+    for (int m = 0; m < nc; ++m) s += dz2[m][j] * pq[m][k];
+    part[OW2 + j * NH + k] = s;
+  }
+  // dp[m][k = j] = sum_i dz2[m][i] * W2[i][j]
+  for (int m = 0; m < nc; ++m) {
+    float s = 0.0f;
+    for (int i = 0; i < NH; ++i) s += dz2[m][i] * bf16_value(W2[(size_t)i * NH + j]);
+    dp[m][j] = s;
+  }
+  __syncthreads();
+  // layer 1: recompute z1 per row, dz1 = dp / rows where z1 > 0
+  float gw1[NF];
+  for (int f = 0; f < NF; ++f) gw1[f] = 0.0f;
+  float gb1 = 0.0f;
+  float w1[NF];
+  for (int f = 0; f < NF; ++f) w1[f] = bf16_value(W1[(size_t)j * KP + f]);
+  const float b1j = L.params[OB1 + j];
+  for (int m = 0; m < nc; ++m) {
+    const int64_t cand = c0 + m;
+    const int rows = L.count[cand] > 0 ? L.count[cand] : 0;
+    const float g = rows > 0 ? dp[m][j] / (float)rows : 0.0f;
+    const uint16_t *X = L.feat + (size_t)cand * L.row_stride * NF;
+    for (int r = 0; r < rows; ++r) {
+      __syncthreads();
+      if (j < NF) xs[j] = bf16_value(X[(size_t)r * NF + j]);
+      __syncthreads();
+      float z = b1j;
+      for (int f = 0; f < NF; ++f) z += w1[f] * xs[f];
+      if (z > 0.0f) {
+        gb1 += g;
+        for (int f = 0; f < NF; ++f) gw1[f] += g * xs[f];
+      }
+    }
+  }
+  for (int f = 0; f < NF; ++f) part[OW1 + j * NF + f] = gw1[f];
+  part[OB1 + j] = gb1;
+  part[OB2 + j] = gb2;
+  part[OW3 + j] = gw3;
+  if (j == 0) {
+    part[OB3] = gb3;
+    part[NPARAM] = lsum;
+  }
+}
+
+// grad[i] = sum over chunks in order; loss = sum of squared errors / n.
+__global__ void reduce_kernel(const float *__restrict__ partial, size_t stride, int chunks,
+                              int64_t n, float *__restrict__ grad, float *__restrict__ loss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > NPARAM) return;
+  float s = 0.0f;
+  for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * stride + i];
+  if (i < NPARAM) {
+    grad[i] = s;
+  } else if (loss) {
+    loss[0] = s / (float)n;
+  }
+}
+
+__global__ void adam_kernel(float *__restrict__ P, uint16_t *__restrict__ Q, float *__restrict__ M,
+                            float *__restrict__ V, const float *__restrict__ G, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NPARAM) return;
+  const float g = G[i];
+  const float m = b1 * M[i] + (1.0f - b1) * g;
+  const float v = b2 * V[i] + (1.0f - b2) * g * g;
+  M[i] = m;
+  V[i] = v;
+  const float mh = m / c1, vh = v / c2;
+  const float p = P[i] - lr * mh / (sqrtf(vh) + eps);
+  P[i] = p;
+  // repack the weight this parameter feeds (biases have no packed copy)
+  if (i < OB1) {
+    Q[PW1 + (i / NF) * KP + (i % NF)] = bf16_rne(p);
+  } else if (i >= OW2 && i < OB2) {
+    Q[PW2 + (i - OW2)] = bf16_rne(p);
+  } else if (i >= OW3 && i < OB3) {
+    Q[PW3 + (i - OW3)] = bf16_rne(p);
+  }
+}
+
+}  // namespace
+
+size_t feat_wave_bytes(const DevBatch &b) {
+  const int NAm = b.max_NA > 0 ? b.max_NA : 1;
+  return (feat_table_bytes(b.max_C, b.max_X, NAm) + 255) & ~(size_t)255;
+}
+
+int launch_features(const FeatLaunch &L, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (L.n_items == 0) return 0;
+  hipLaunchKernelGGL(features_kernel, dim3(L.grid), dim3(kWave), 0, st, L);
+  return (int)hipGetLastError();
+}
+
+int launch_pack(const float *params, uint16_t *packed, void *stream) {
+  hipLaunchKernelGGL(pack_kernel, dim3((NPACK + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     params, packed);
+  return (int)hipGetLastError();
+}
+
+int launch_forward(const FwdLaunch &L, void *stream) {
+  if (L.n == 0) return 0;
+  const int64_t blocks = (L.n + 15) / 16;
+  hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kWave), 0, (hipStream_t)stream,
+                     L);
+  return (int)hipGetLastError();
+}
+
+size_t backward_partial_stride() { return ((size_t)NPARAM + 1 + 63) & ~(size_t)63; }
+int64_t backward_chunks(int64_t n) { return (n + kBwdChunk - 1) / kBwdChunk; }
+
+int launch_backward(const BwdLaunch &L, float *grad, float *loss, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (L.n == 0) return 0;
+  const int64_t chunks = backward_chunks(L.n);
+  hipLaunchKernelGGL(backward_kernel, dim3((unsigned)chunks), dim3(256), 0, st, L);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(reduce_kernel, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, st,
+                     (const float *)L.partial, L.part_stride, (int)chunks, L.n, grad, loss);
+  return (int)hipGetLastError();
+}
+
+int launch_adam(float *P, uint16_t *Q, float *M, float *V, const float *G, float lr, float b1,
+                float b2, float eps, int64_t step, void *stream) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, P,
+                     Q, M, V, G, lr, b1, b2, eps, c1, c2);
+  return (int)hipGetLastError();
+}
+
+}  // namespace paam

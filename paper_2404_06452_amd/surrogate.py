@@ -1,0 +1,129 @@
+"""Training and use of the candidate-ranking network on the GPU.
+
+Every step runs in libpaam's kernels: targets come from the exact analysis
+(``paam_candidate_wcrt``, every chain's bound at cap 2D, target =
+min(max R/D, 2)), inputs from ``paam_features``, and the network is trained by
+``paam_mlp_forward`` / ``paam_mlp_backward`` / ``paam_mlp_adam_step``.  This
+module only orders the calls, draws nothing itself (pairs and initial weights
+come from the seeded input generators) and moves batch indices around.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import _paam
+
+
+class Trainer:
+    """Mean-squared-error training of the ranking network on (set, k,
+    util_permille) pairs of one uploaded batch."""
+
+    def __init__(self, dev: _paam.Chainset, net: _paam.Network, seed: int, batch: int = 4096,
+                 stream=None):
+        import torch
+        self.dev, self.net, self.seed, self.batch, self.stream = dev, net, seed, batch, stream
+        d = dev.device
+        self.rs = dev.max_chains
+        self.feat = torch.zeros(batch * self.rs * _paam.N_FEAT, dtype=torch.int16, device=d)
+        self.count = torch.zeros(batch, dtype=torch.int32, device=d)
+        self.out = torch.zeros(batch, dtype=torch.float32, device=d)
+        self.act = torch.zeros(batch * 512, dtype=torch.int16, device=d)
+        self.grad = torch.zeros(_paam.MLP_PARAMS, dtype=torch.float32, device=d)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=d)
+        self.fws = _paam.workspace(_paam.paam_features_bytes(dev, batch), d)
+        self.bws = _paam.workspace(_paam.paam_mlp_backward_bytes(batch), d)
+
+    def targets(self, pairs, cap_mult: int = 2):
+        """Exact-analysis targets of device pairs [n, 3]: float32 ratios."""
+        o = _paam.wcrt_opts(cap_mult=cap_mult, full=True)
+        n = int(pairs.shape[0])
+        out = _paam.CandOut(n, self.dev.device)
+        ws = _paam.workspace(_paam.paam_candidate_bytes(self.dev, o, n), self.dev.device)
+        _paam.paam_candidate_wcrt(self.dev, o, self.seed, pairs, out, ws, self.stream)
+        return out
+
+    def _features(self, pairs):
+        _paam.paam_features(self.dev, self.seed, pairs, self.rs, self.feat, self.count, self.fws,
+                            self.stream)
+
+    def step(self, pairs, target, lr: float) -> None:
+        """One Adam step on a batch (device pairs [b, 3], target [b])."""
+        b = int(pairs.shape[0])
+        self._features(pairs)
+        _paam.paam_mlp_forward(self.net.params, self.net.packed, self.feat, self.count, b, self.rs,
+                               self.out, self.act, self.stream)
+        _paam.paam_mlp_backward(self.net.params, self.net.packed, self.feat, self.count, b,
+                                self.rs, self.out, target, self.act, self.grad, self.loss,
+                                self.bws, self.stream)
+        self.net.adam(self.grad, lr, stream=self.stream)
+
+    def predict(self, pairs):
+        """Network outputs for device pairs (float32 device tensor)."""
+        import torch
+        n = int(pairs.shape[0])
+        res = torch.empty(n, dtype=torch.float32, device=self.dev.device)
+        for i in range(0, n, self.batch):
+            p = pairs[i:i + self.batch]
+            b = int(p.shape[0])
+            self._features(p)
+            _paam.paam_mlp_forward(self.net.params, self.net.packed, self.feat, self.count, b,
+                                   self.rs, res[i:i + b], None, self.stream)
+        return res
+
+    def fit(self, pairs, target, epochs: int, lr: float, order_seed: int, log=None,
+            lr_final: float | None = None):
+        """Epochs over device pairs/targets in a seeded shuffled order; the
+        learning rate decays linearly to lr_final.  Returns the mean loss of
+        every epoch."""
+        import torch
+        n = int(pairs.shape[0])
+        g = torch.Generator(device="cpu")
+        g.manual_seed(order_seed)
+        steps = epochs * ((n + self.batch - 1) // self.batch)
+        k = 0
+        losses = []
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=g).to(pairs.device)
+            acc = torch.zeros(1, dtype=torch.float64, device=pairs.device)
+            t0 = time.perf_counter()
+            nb = 0
+            for i in range(0, n, self.batch):
+                idx = perm[i:i + self.batch]
+                if idx.numel() < 2:
+                    continue
+                cur = lr if lr_final is None else lr + (lr_final - lr) * k / max(steps - 1, 1)
+                self.step(pairs[idx].contiguous(), target[idx].contiguous(), float(cur))
+                acc += self.loss.double()
+                nb += 1
+                k += 1
+            losses.append(float(acc.item()) / max(nb, 1))
+            if log:
+                log("epoch %d: loss %.5f (%.1f s)" % (ep, losses[-1], time.perf_counter() - t0))
+        return losses
+
+
+def spearman(a, b) -> float:
+    """Spearman rank correlation of two 1-D arrays (average ranks for ties)."""
+    def ranks(x):
+        x = np.asarray(x, np.float64)
+        order = np.argsort(x, kind="stable")
+        r = np.empty(len(x))
+        r[order] = np.arange(len(x))
+        # average ranks of ties
+        xs = x[order]
+        i = 0
+        while i < len(xs):
+            j = i
+            while j + 1 < len(xs) and xs[j + 1] == xs[i]:
+                j += 1
+            if j > i:
+                r[order[i:j + 1]] = (i + j) / 2.0
+            i = j + 1
+        return r
+    ra, rb = ranks(a), ranks(b)
+    ra -= ra.mean()
+    rb -= rb.mean()
+    den = np.sqrt((ra * ra).sum() * (rb * rb).sum())
+    return float((ra * rb).sum() / den) if den > 0 else 0.0

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(_paam.LIBPAAM)
     missing = [n for n in declared_entry_points() if not hasattr(lib, n)]
     assert not missing, missing
-    assert set(_paam.EXPORTED) <= set(declared_entry_points())
+    assert set(_paam.EXPORTED) == set(declared_entry_points())
     assert b"gfx950" in _paam.lib().paam_version()
 
 
@@ -42,6 +42,19 @@ def test_errors_are_reported_without_a_device():
     n = ctypes.c_size_t(0)
     assert L.paam_chainset_bytes(None, ctypes.byref(n)) == -1
     assert b"null" in L.paam_last_error()
+
+
+def test_surrogate_entry_points_reject_bad_arguments():
+    from paper_2404_06452_amd import _paam
+    L = _paam.lib()
+    n = ctypes.c_size_t(0)
+    assert L.paam_mlp_backward_bytes(-1, ctypes.byref(n)) == -1
+    assert L.paam_mlp_backward_bytes(1000, ctypes.byref(n)) == 0 and n.value > 1000
+    assert L.paam_mlp_pack(None, None, None) == -1
+    assert L.paam_mlp_adam_step(None, None, None, None, None, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -1
+    assert L.paam_mlp_forward(None, None, None, None, -1, 1, None, None, None) == -1
+    assert L.paam_candidate_bytes(None, None, 1, ctypes.byref(n)) == -1
+    assert L.paam_features_bytes(None, 1, ctypes.byref(n)) == -1
 
 
 def test_bytes_query_validates_the_problem_statement():
