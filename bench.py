@@ -81,6 +81,123 @@ def copy_calibration(torch, stream):
     return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
 
 
+def search_section(args, torch, log):
+    """Priority-order search over 256 candidate orders per set, plain and
+    guided by the ranking network (trained here by the library's kernels),
+    at the workload's utilisation and at a scale near the feasibility
+    boundary.  Times are HIP events on the launch stream."""
+    from paper_2404_06452_amd import _paam, chaingen, surrogate
+
+    n_cand, top_k, seed = 256, 16, 2404
+    stream = torch.cuda.Stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    t0 = time.perf_counter()
+    cs = chaingen.generate("search", args.search_sets)
+    dev = _paam.Chainset(cs, device="cuda:0")
+    n = cs.n_sets
+    out = _paam.SearchOut(dev)
+    scores = torch.empty(n * n_cand, dtype=torch.float32, device="cuda:0")
+
+    def run_search(util, guided, fallback=True):
+        o = _paam.search_opts(n_cand, seed, guided=guided, top_k=top_k, fallback=fallback,
+                              scores=scores if guided else None, util_permille=util)
+        ws = _paam.workspace(_paam.paam_search_bytes(dev, o))
+        dt = timed(lambda: _paam.paam_priority_search(dev, o, out, ws, stream))
+        return dt, out.found.cpu().numpy(), out.n_exact.cpu().numpy()
+
+    def run_score(net, util):
+        o = _paam.search_opts(n_cand, seed, util_permille=util)
+        ws = _paam.workspace(_paam.paam_score_bytes(dev, o))
+        return timed(lambda: _paam.paam_score_candidates(dev, o, net.params, net.packed, scores,
+                                                         ws, stream))
+
+    # the ranking network, trained on the sweep generator's sets
+    t1 = time.perf_counter()
+    tcs = chaingen.generate("sweep", args.train_sets)
+    tdev = _paam.Chainset(tcs, device="cuda:0")
+    net = _paam.Network(chaingen.mlp_init(seed), device="cuda:0")
+    tr = surrogate.Trainer(tdev, net, seed, batch=4096)
+    pairs = torch.from_numpy(surrogate.recipe_pairs(tcs.n_sets, args.train_samples, seed)).cuda()
+    t_targets = timed(lambda: setattr(tr, "_tg", tr.targets(pairs)))
+    target = tr._tg.ratio[:args.train_samples]
+    t2 = time.perf_counter()
+    losses = tr.fit(pairs, target, epochs=args.train_epochs, lr=2e-3, lr_final=1e-4,
+                    order_seed=seed, log=log)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t2
+    hcs = chaingen.generate("sweep", 20000, set_begin=args.train_sets)
+    hdev = _paam.Chainset(hcs, device="cuda:0")
+    htr = surrogate.Trainer(hdev, net, seed, batch=4096)
+    hp = torch.from_numpy(surrogate.recipe_pairs(hcs.n_sets, 200000, seed + 1)).cuda()
+    hy = htr.targets(hp).ratio[:200000].cpu().numpy()
+    hpred = htr.predict(hp).cpu().numpy()
+    sur = {
+        "train_sets": tcs.n_sets, "train_samples": args.train_samples,
+        "epochs": args.train_epochs, "target_s": t_targets, "train_s": t_fit,
+        "epoch_losses": losses, "holdout_samples": len(hy),
+        "holdout_mae": float(np.mean(np.abs(hpred - hy))),
+        "holdout_spearman": surrogate.spearman(hpred, hy),
+        "recipe": "sweep-generator sets at utilisation 0.2-10 % (log-uniform) of their U=1 "
+                  "draw, k uniform in 0..255, target min(max R/D, 2)",
+    }
+    log("surrogate: trained in %.1f s (targets %.2f s), holdout MAE %.3f, Spearman %.3f" % (
+        time.perf_counter() - t1, t_targets, sur["holdout_mae"], sur["holdout_spearman"]))
+    untrained = _paam.Network(chaingen.mlp_init(seed + 7), device="cuda:0")
+
+    res = {"workload": "%d chain sets of 16 chains x 2-8 callbacks, 4 executors, 1 accelerator, "
+                       "U ~ U(0.5, 0.9); %d candidate orders per set (uploaded rate-monotonic "
+                       "order + seeded swap walk); guided: top %d by predicted max R/D" % (
+                           n, n_cand, top_k),
+           "surrogate": sur}
+    for name, util in (("workload_utilisation", 1000), ("near_boundary_5pct", 50)):
+        t_plain, f_plain, e_plain = run_search(util, False)
+        found_plain = f_plain >= 0
+        t_score = run_score(net, util)
+        t_fb, f_fb, e_fb = run_search(util, True, True)
+        t_top, f_top, e_top = run_search(util, True, False)
+        rel = (lambda f: float((f >= 0).sum() / max(found_plain.sum(), 1)))
+        entry = {
+            "util_scale": util / 1000,
+            "plain": {"sets_per_s": n / t_plain, "ms": t_plain * 1e3,
+                      "found_frac": float(found_plain.mean()),
+                      "mean_exact_evals": float(e_plain.mean())},
+            "guided_with_fallback": {"sets_per_s": n / (t_score + t_fb), "score_ms": t_score * 1e3,
+                                     "search_ms": t_fb * 1e3, "found_frac": float((f_fb >= 0).mean()),
+                                     "found_vs_plain": rel(f_fb),
+                                     "mean_exact_evals": float(e_fb.mean())},
+            "guided_top_k_only": {"sets_per_s": n / (t_score + t_top), "score_ms": t_score * 1e3,
+                                  "search_ms": t_top * 1e3, "found_frac": float((f_top >= 0).mean()),
+                                  "found_vs_plain": rel(f_top),
+                                  "mean_exact_evals": float(e_top.mean())},
+        }
+        if util != 1000:
+            run_score(untrained, util)
+            _, f_un, e_un = run_search(util, True, False)
+            entry["untrained_network_top_k_only"] = {"found_frac": float((f_un >= 0).mean()),
+                                                     "found_vs_plain": rel(f_un),
+                                                     "mean_exact_evals": float(e_un.mean())}
+        res[name] = entry
+        log("search %s: plain %.3g sets/s found %.3f evals %.1f | guided+fb %.3g sets/s found %.3f "
+            "evals %.1f | top-%d %.3g sets/s found %.3f" % (
+                name, entry["plain"]["sets_per_s"], entry["plain"]["found_frac"],
+                entry["plain"]["mean_exact_evals"], entry["guided_with_fallback"]["sets_per_s"],
+                entry["guided_with_fallback"]["found_frac"],
+                entry["guided_with_fallback"]["mean_exact_evals"], top_k,
+                entry["guided_top_k_only"]["sets_per_s"], entry["guided_top_k_only"]["found_frac"]))
+    res["setup_s"] = time.perf_counter() - t0
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +207,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1000, help="sets per level for the oracle")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--search-sets", type=int, default=100_000)
+    ap.add_argument("--train-sets", type=int, default=200_000)
+    ap.add_argument("--train-samples", type=int, default=10_000_000)
+    ap.add_argument("--train-epochs", type=int, default=2)
+    ap.add_argument("--skip-search", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the analysis shards across GPUs by set range with no "
@@ -244,6 +366,10 @@ def main():
                       "mode" % (n_s, len(levels), n_s * len(levels)),
         },
     }
+    if not args.skip_search:
+        del graph, eager, dev, outs, ws, vout
+        torch.cuda.empty_cache()
+        line["search"] = search_section(args, torch, log)
     print(json.dumps(line), flush=True)
     if mism:
         sys.exit(1)

@@ -334,3 +334,22 @@ def random_scores(n: int, seed: int, ties: bool = False) -> np.ndarray:
     if ties:
         return rng.integers(0, 8, n).astype(np.float32) / 4.0
     return rng.uniform(0.0, 2.0, n).astype(np.float32)
+
+
+def training_triples(n_sets: int, n_samples: int, n_cand: int, util_range: tuple[int, int],
+                     seed: int) -> np.ndarray:
+    """int64 [n_samples, 3]: (set, candidate k, util_permille), set and k
+    uniform, util_permille log-uniform over util_range (integers)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((n_samples, 3), np.int64)
+    out[:, 0] = rng.integers(0, n_sets, n_samples)
+    out[:, 1] = rng.integers(0, n_cand, n_samples)
+    lo, hi = np.log(util_range[0]), np.log(util_range[1] + 1)
+    out[:, 2] = np.clip(np.floor(np.exp(rng.uniform(lo, hi, n_samples))), util_range[0],
+                        util_range[1]).astype(np.int64)
+    return out
+
+
+def shuffle_order(n: int, seed: int) -> np.ndarray:
+    """int64 [n]: a seeded permutation (the visiting order of one epoch)."""
+    return np.random.default_rng(seed).permutation(n).astype(np.int64)

@@ -678,6 +678,18 @@ static int grid_items(int64_t n_items, int waves_per_cu) {
   return (int)std::max<int64_t>(g, 1);
 }
 
+// Features grid: with LDS tables, as many waves per CU as the LDS holds (at
+// most 12, the register limit of the kernel); else 8.
+static int feat_grid(const paam_chainset *cs, int64_t n_items) {
+  int w = 8;
+  if (paam::feat_in_lds(cs->dev)) {
+    const size_t per = paam::feat_wave_bytes(cs->dev);
+    w = (int)std::min<size_t>(12, (160 * 1024) / std::max<size_t>(per, 1));
+    w = std::max(w, 1);
+  }
+  return grid_items(n_items, w);
+}
+
 static bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 paam_status paam_candidate_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, int64_t n_pairs,
@@ -728,7 +740,7 @@ paam_status paam_candidate_wcrt(const paam_chainset *cs, const paam_wcrt_opts *o
 paam_status paam_features_bytes(const paam_chainset *cs, int64_t n_pairs, size_t *ws_bytes) {
   if (!cs || !ws_bytes) return fail(PAAM_E_INVAL, "null argument");
   if (n_pairs < 0) return fail(PAAM_E_INVAL, "n_pairs < 0");
-  *ws_bytes = 256 + (size_t)grid_items(n_pairs, 0) * paam::feat_wave_bytes(cs->dev);
+  *ws_bytes = 256 + (size_t)feat_grid(cs, n_pairs) * paam::feat_wave_bytes(cs->dev);
   return PAAM_OK;
 }
 
@@ -763,7 +775,7 @@ paam_status paam_features(const paam_chainset *cs, uint64_t seed, const int64_t 
   L.counter = static_cast<unsigned long long *>(d_ws);
   L.scratch = static_cast<unsigned char *>(d_ws) + 256;
   L.scratch_stride = paam::feat_wave_bytes(cs->dev);
-  L.grid = grid_items(n_pairs, 0);
+  L.grid = feat_grid(cs, n_pairs);
   int e = paam::launch_features(L, stream);
   if (e != 0) return hip_fail((hipError_t)e, "features launch");
   return PAAM_OK;
@@ -852,7 +864,7 @@ paam_status paam_score_bytes(const paam_chainset *cs, const paam_search_opts *o,
   const int64_t items = S * ((o->n_cand + 63) / 64);
   const size_t feat = ((size_t)pairs * std::max(cs->dev.max_C, 1) * 48 * 2 + 255) & ~(size_t)255;
   const size_t cnt = ((size_t)pairs * 4 + 255) & ~(size_t)255;
-  *ws_bytes = 256 + feat + cnt + (size_t)grid_items(items, 0) * paam::feat_wave_bytes(cs->dev);
+  *ws_bytes = 256 + feat + cnt + (size_t)feat_grid(cs, items) * paam::feat_wave_bytes(cs->dev);
   return PAAM_OK;
 }
 
@@ -894,7 +906,7 @@ paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opt
     F.counter = reinterpret_cast<unsigned long long *>(w);
     F.scratch = scr;
     F.scratch_stride = paam::feat_wave_bytes(cs->dev);
-    F.grid = grid_items(F.n_items, 0);
+    F.grid = feat_grid(cs, F.n_items);
     int e = paam::launch_features(F, stream);
     if (e != 0) return hip_fail((hipError_t)e, "features launch");
     paam::FwdLaunch L{d_params, d_packed, feat, count, ns * o->n_cand, Cm,

@@ -163,6 +163,10 @@ struct BwdLaunch {
 };
 
 size_t feat_wave_bytes(const DevBatch &b);
+// Feature tables of up to this size per wave live in LDS (else in the wave's
+// global scratch); the host sizes the grid for the LDS it takes.
+constexpr size_t kFeatLdsMax = 40 * 1024;
+bool feat_in_lds(const DevBatch &b);
 size_t backward_partial_stride();
 int64_t backward_chunks(int64_t n);
 int launch_features(const FeatLaunch &L, void *stream);

@@ -17,26 +17,41 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ features
 
-// Per-wave tables of one set, independent of the priority order.
+// A wave computes the features of up to kMaxGroup consecutive candidates of a
+// set at once: lane g*C + c holds chain c of candidate g (one candidate per
+// pass when C > 64).
+constexpr int kMaxGroup = 16;
+
+// Per-wave tables: a set's order-independent totals (built once per set), the
+// walk state, and the ranks and bucket levels of the group's candidates.
 struct FeatTables {
-  int64_t *Ec, *Acc, *epc, *Emax, *qsum, *qasum;  // [Cm]
-  int32_t *S, *dl, *ncb, *mine, *uses;             // [Cm]
-  int64_t *Ece, *Acce, *epce, *bl, *bS, *q, *qa;  // [Cm][Xm]
-  int32_t *runs;                                   // [Cm][Xm]
-  int64_t *Ahat, *Amax, *qA;                       // [Cm][NAm]
-  int32_t *dca, *nra, *level;                      // [Cm][NAm]
-  int32_t *order, *buf;                            // [Cm], [64]
-  int16_t *rank;                                   // [Cm]
+  int64_t *Ec, *Acc, *epc, *Emax, *qsum, *qasum, *T, *D;  // [Cm]
+  int64_t *Ece, *Acce, *epce, *bl, *bS, *q, *qa;          // [Cm][X]
+  int64_t *Ahat, *Amax, *qA;                               // [Cm][NA]
+  int64_t *setv;                                           // [8] set-level sums
+  int32_t *S, *dl, *ncb, *mine, *uses, *spin;              // [Cm]
+  int32_t *runs;                                           // [Cm][X]
+  int32_t *dca, *nra;                                      // [Cm][NA]
+  int32_t *hpx;                                            // [Xm]
+  int32_t *order, *buf;                                    // [Cm], [64]
+  int32_t *levelg;                                         // [max(64, Cm)][NA]
+  int16_t *rank;                                           // [Cm]
+  int16_t *rankg;                                          // [max(64, Cm)]
 };
 
 __host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
   const size_t C = Cm, CX = (size_t)Cm * Xm, CA = (size_t)Cm * NAm;
-  return 8 * (6 * C + 7 * CX + 3 * CA) + 4 * (5 * C + CX + 3 * CA + C + 64) + 2 * C + 64;
+  const size_t G = Cm > 64 ? (size_t)Cm : 64;
+  const size_t n64 = 8 * C + 7 * CX + 3 * CA + 8;
+  const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G * NAm;
+  const size_t n16 = C + G;
+  return ((8 * n64 + 4 * n32 + 2 * n16) + 15) & ~(size_t)15;
 }
 
 __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   FeatTables t;
   const size_t C = Cm, CX = (size_t)Cm * Xm, CA = (size_t)Cm * NAm;
+  const size_t G = Cm > 64 ? (size_t)Cm : 64;
   int64_t *d = reinterpret_cast<int64_t *>(base);
   t.Ec = d; d += C;
   t.Acc = d; d += C;
@@ -44,6 +59,8 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.Emax = d; d += C;
   t.qsum = d; d += C;
   t.qasum = d; d += C;
+  t.T = d; d += C;
+  t.D = d; d += C;
   t.Ece = d; d += CX;
   t.Acce = d; d += CX;
   t.epce = d; d += CX;
@@ -54,19 +71,24 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.Ahat = d; d += CA;
   t.Amax = d; d += CA;
   t.qA = d; d += CA;
+  t.setv = d; d += 8;
   int32_t *i = reinterpret_cast<int32_t *>(d);
   t.S = i; i += C;
   t.dl = i; i += C;
   t.ncb = i; i += C;
   t.mine = i; i += C;
   t.uses = i; i += C;
+  t.spin = i; i += C;
   t.runs = i; i += CX;
   t.dca = i; i += CA;
   t.nra = i; i += CA;
-  t.level = i; i += CA;
+  t.hpx = i; i += Xm;
   t.order = i; i += C;
   t.buf = i; i += 64;
-  t.rank = reinterpret_cast<int16_t *>(i);
+  t.levelg = i; i += G * NAm;
+  int16_t *h = reinterpret_cast<int16_t *>(i);
+  t.rank = h; h += C;
+  t.rankg = h;
   return t;
 }
 
@@ -82,17 +104,19 @@ __device__ __forceinline__ double fratio(int64_t n, int64_t m) {
 constexpr int64_t kQ = 65536;  // fixed-point scale of utilisation terms
 
 // Order-independent tables of a set at utilisation scale u.  Lane c owns the
-// rows of chain c.  Ends synchronised.
+// rows of chain c; lane 0 then forms the set-level sums.  Ends synchronised.
 __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables &t) {
   const int64_t c0 = b.set_chain_off[set];
   const int C = (int)(b.set_chain_off[set + 1] - c0);
-  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
+  const int64_t x0 = b.set_exec_off[set];
+  const int X = (int)(b.set_exec_off[set + 1] - x0);
   const int64_t a0 = b.set_accel_off[set];
   const int NA = (int)(b.set_accel_off[set + 1] - a0);
   const int NAm = NA > 0 ? NA : 1;
   const int64_t cb0 = b.set_cb_off[set];
   const int64_t run0 = b.set_run_off[set];
   const int nrun = (int)(b.set_run_off[set + 1] - run0);
+  for (int e = threadIdx.x; e < X; e += kWave) t.hpx[e] = (int32_t)b.hpx_mask[x0 + e];
   for (int c = threadIdx.x; c < C; c += kWave) {
     int64_t E = 0, Ac = 0, ep = 0, Emax = 0;
     int S = 0, dl = 0, ncb = 0;
@@ -160,11 +184,36 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
     t.Emax[c] = Emax;
     t.qsum[c] = qs;
     t.qasum[c] = qas;
+    t.T[c] = T;
+    t.D[c] = b.D[c0 + c];
     t.S[c] = S;
     t.dl[c] = dl;
     t.ncb[c] = ncb;
     t.mine[c] = (int32_t)mine;
     t.uses[c] = (int32_t)uses;
+    t.spin[c] = b.spin[c0 + c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t sum_q = 0, sum_qA = 0, sum_dem = 0, Tmin = INT64_MAX, max_qe = 0, tot = 0;
+    for (int h = 0; h < C; ++h) {
+      tot += t.Ec[h] + t.Acc[h] + t.epc[h];
+      sum_q += t.qsum[h];
+      for (int a = 0; a < NA; ++a) sum_qA += t.qA[h * NAm + a];
+      sum_dem += t.Ec[h] + t.Acc[h];
+      Tmin = t.T[h] < Tmin ? t.T[h] : Tmin;
+    }
+    for (int e = 0; e < X; ++e) {
+      int64_t s = 0;
+      for (int h = 0; h < C; ++h) s += t.q[h * X + e];
+      max_qe = s > max_qe ? s : max_qe;
+    }
+    t.setv[0] = sum_q;
+    t.setv[1] = sum_qA;
+    t.setv[2] = sum_dem;
+    t.setv[3] = Tmin;
+    t.setv[4] = max_qe;
+    t.setv[5] = tot;
   }
   __syncthreads();
 }
@@ -173,197 +222,160 @@ __device__ __forceinline__ void put_feat(uint16_t *row, int f, double v) {
   row[f] = bf16_rne((float)v);
 }
 
-// The 48 features of every chain of a set under the order in t.order/t.rank,
-// written to rows out[c * 48 ...].  Feature k here is feature k of the
-// documented list; each is (double)N / (double)M of exact integers.  Returns
-// false (and writes nothing) when the set's total demand reaches 2^40, where
-// the integer numerators could overflow.
-__device__ bool feat_candidate(const DevBatch &b, int64_t set, FeatTables &t, uint16_t *out) {
-  const int64_t c0 = b.set_chain_off[set];
-  const int C = (int)(b.set_chain_off[set + 1] - c0);
-  const int64_t x0 = b.set_exec_off[set];
-  const int X = (int)(b.set_exec_off[set + 1] - x0);
+// The 48 features of chain c under the candidate whose ranks are rk and
+// bucket levels lv, written to row[0..47].  Feature k here is feature k of
+// the documented list; each is (double)N / (double)M of exact integers.
+__device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, const int16_t *rk,
+                           const int32_t *lv, int c, uint16_t *row) {
+  const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
+  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
   const int64_t a0 = b.set_accel_off[set];
   const int NA = (int)(b.set_accel_off[set + 1] - a0);
   const int NAm = NA > 0 ? NA : 1;
   const int64_t hop = b.eps_hop[set];
-  // bucket level of every (chain, accelerator) under this order (Sec. IV-C)
-  for (int c = threadIdx.x; c < C; c += kWave) {
-    const int rho = t.rank[c];
-    for (int a = 0; a < NA; ++a) {
-      int lev = -1;
-      if (t.dca[c * NAm + a] > 0) {
-        int r = 0, m = 0;
-        for (int h = 0; h < C; ++h) {
-          if (t.dca[h * NAm + a] > 0) {
-            ++m;
-            if (t.rank[h] < rho) ++r;
-          }
-        }
-        lev = (int)(((int64_t)r * b.buckets[a0 + a]) / m);
-      }
-      t.level[c * NAm + a] = lev;
-    }
-  }
-  __syncthreads();
-  // set-level sums (identical on every lane)
-  int64_t sum_q = 0, sum_qA = 0, sum_dem = 0, Tmin = INT64_MAX, max_qe = 0, tot = 0;
+  const int rho = rk[c];
+  const int64_t T = t.T[c], D = t.D[c];
+  const int S = t.S[c];
+  const int64_t own = t.Ec[c] + t.Acc[c] + t.epc[c] + (int64_t)(S - 1) * hop;
+  const uint32_t mine = (uint32_t)t.mine[c], uses = (uint32_t)t.uses[c];
+  put_feat(row, 0, fratio(t.Ec[c], D));
+  put_feat(row, 1, fratio(t.Acc[c], D));
+  put_feat(row, 2, fratio(t.epc[c], D));
+  put_feat(row, 3, fratio((int64_t)(S - 1) * hop, D));
+  put_feat(row, 4, fratio(own, D));
+  put_feat(row, 5, fratio(t.Emax[c], D));
+  put_feat(row, 6, fratio(S, 16));
+  put_feat(row, 7, fratio(t.dl[c], 16));
+  put_feat(row, 8, fratio(t.ncb[c], 32));
+  put_feat(row, 9, fratio(__popc(mine), X));
+  put_feat(row, 10, fratio(D, T));
+  put_feat(row, 11, fratio(T, (int64_t)1 << 30));
+  put_feat(row, 12, t.spin[c] ? 1.0 : 0.0);
+  put_feat(row, 13, fratio(t.qsum[c], kQ));
+  put_feat(row, 14, fratio(t.qasum[c], kQ));
+  put_feat(row, 15, fratio(rho, C));
+  put_feat(row, 16, fratio(C - 1 - rho, C));
+  put_feat(row, 17, rho == 0 ? 1.0 : 0.0);
+  put_feat(row, 18, rho == C - 1 ? 1.0 : 0.0);
+  int n19 = 0, n20 = 0;
   for (int h = 0; h < C; ++h) {
-    tot += t.Ec[h] + t.Acc[h] + t.epc[h];
-    sum_q += t.qsum[h];
-    for (int a = 0; a < NA; ++a) sum_qA += t.qA[h * NAm + a];
-    sum_dem += t.Ec[h] + t.Acc[h];
-    const int64_t Th = b.T[c0 + h];
-    Tmin = Th < Tmin ? Th : Tmin;
+    const int64_t Th = t.T[h];
+    const int rh = rk[h];
+    n19 += (rh < rho && Th > T) ? 1 : 0;
+    n20 += (rh > rho && Th < T) ? 1 : 0;
   }
-  if (tot >= ((int64_t)1 << 40)) return false;
+  put_feat(row, 19, fratio(n19, C));
+  put_feat(row, 20, fratio(n20, C));
+  // hp on the chain's executors, blocking, hpp
+  int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0, n_hpp = 0, q_hpp = 0;
+  int n25 = 0, n29 = 0;
   for (int e = 0; e < X; ++e) {
-    int64_t s = 0;
-    for (int h = 0; h < C; ++h) s += t.q[h * X + e];
-    max_qe = s > max_qe ? s : max_qe;
-  }
-  for (int c = threadIdx.x; c < C; c += kWave) {
-    uint16_t *row = out + (size_t)c * 48;
-    const int rho = t.rank[c];
-    const int64_t T = b.T[c0 + c], D = b.D[c0 + c];
-    const int spin_c = b.spin[c0 + c];
-    const int S = t.S[c];
-    const int64_t own = t.Ec[c] + t.Acc[c] + t.epc[c] + (int64_t)(S - 1) * hop;
-    const uint32_t mine = (uint32_t)t.mine[c], uses = (uint32_t)t.uses[c];
-    put_feat(row, 0, fratio(t.Ec[c], D));
-    put_feat(row, 1, fratio(t.Acc[c], D));
-    put_feat(row, 2, fratio(t.epc[c], D));
-    put_feat(row, 3, fratio((int64_t)(S - 1) * hop, D));
-    put_feat(row, 4, fratio(own, D));
-    put_feat(row, 5, fratio(t.Emax[c], D));
-    put_feat(row, 6, fratio(S, 16));
-    put_feat(row, 7, fratio(t.dl[c], 16));
-    put_feat(row, 8, fratio(t.ncb[c], 32));
-    put_feat(row, 9, fratio(__popc(mine), X));
-    put_feat(row, 10, fratio(D, T));
-    put_feat(row, 11, fratio(T, (int64_t)1 << 30));
-    put_feat(row, 12, spin_c ? 1.0 : 0.0);
-    put_feat(row, 13, fratio(t.qsum[c], kQ));
-    put_feat(row, 14, fratio(t.qasum[c], kQ));
-    put_feat(row, 15, fratio(rho, C));
-    put_feat(row, 16, fratio(C - 1 - rho, C));
-    put_feat(row, 17, rho == 0 ? 1.0 : 0.0);
-    put_feat(row, 18, rho == C - 1 ? 1.0 : 0.0);
-    int n19 = 0, n20 = 0;
+    const int64_t rce = t.runs[c * X + e];
+    int64_t sq = 0, sqa = 0, scar = 0, mbl = 0, mbs = 0;
+    int nhp = 0, nlp = 0;
     for (int h = 0; h < C; ++h) {
-      const int64_t Th = b.T[c0 + h];
-      if (t.rank[h] < rho && Th > T) ++n19;
-      if (t.rank[h] > rho && Th < T) ++n20;
+      const int ih = h * X + e;
+      const int rh = rk[h];
+      if (rh < rho) {
+        sq += t.q[ih];
+        sqa += t.qa[ih];
+        scar += t.Ece[ih] + t.Acce[ih] + t.epce[ih];
+        nhp += t.runs[ih] > 0;
+      } else if (rh > rho) {
+        mbl = t.bl[ih] > mbl ? t.bl[ih] : mbl;
+        mbs = t.bS[ih] > mbs ? t.bS[ih] : mbs;
+        nlp += t.runs[ih] > 0;
+      }
     }
-    put_feat(row, 19, fratio(n19, C));
-    put_feat(row, 20, fratio(n20, C));
-    // hp on the chain's executors, blocking, hpp
-    int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0, n_hpp = 0,
-            q_hpp = 0;
-    int n25 = 0, n29 = 0;
-    for (int e = 0; e < X; ++e) {
-      const int64_t rce = t.runs[c * X + e];
-      int64_t sq = 0, sqa = 0, scar = 0, mbl = 0, mbs = 0;
-      int nhp = 0, nlp = 0;
+    n_carry += rce * 2 * scar;
+    n_bp += rce * mbl;
+    n_bs += rce * mbs;
+    if (rce > 0) {
+      q21 += sq;
+      q22 += sqa;
+      q24 = sq + sqa > q24 ? sq + sqa : q24;
+      n25 += nhp;
+      n29 += nlp;
+      m28 = mbs > m28 ? mbs : m28;
+    }
+    for (uint32_t m = (uint32_t)t.hpx[e]; m; m &= m - 1) {
+      const int e2 = __ffs(m) - 1;
       for (int h = 0; h < C; ++h) {
-        const int ih = h * X + e;
-        if (t.rank[h] < rho) {
-          sq += t.q[ih];
-          sqa += t.qa[ih];
-          scar += t.Ece[ih] + t.Acce[ih] + t.epce[ih];
-          nhp += t.runs[ih] > 0;
-        } else if (t.rank[h] > rho) {
-          mbl = t.bl[ih] > mbl ? t.bl[ih] : mbl;
-          mbs = t.bS[ih] > mbs ? t.bS[ih] : mbs;
-          nlp += t.runs[ih] > 0;
-        }
-      }
-      n_carry += rce * 2 * scar;
-      n_bp += rce * mbl;
-      n_bs += rce * mbs;
-      if (rce > 0) {
-        q21 += sq;
-        q22 += sqa;
-        q24 = sq + sqa > q24 ? sq + sqa : q24;
-        n25 += nhp;
-        n29 += nlp;
-        m28 = mbs > m28 ? mbs : m28;
-      }
-      for (uint32_t m = b.hpx_mask[x0 + e]; m; m &= m - 1) {
-        const int e2 = __ffs(m) - 1;
-        for (int h = 0; h < C; ++h) {
-          if (h == c) continue;
-          const int ih = h * X + e2;
-          const bool sp = b.spin[c0 + h] != 0;
-          const int64_t w = t.Ece[ih] + (sp ? t.Acce[ih] + t.epce[ih] : t.epce[ih]);
-          n_hpp += rce * 2 * w;
-          if (rce > 0) q_hpp += t.q[ih] + (sp ? t.qa[ih] : 0);
-        }
+        if (h == c) continue;
+        const int ih = h * X + e2;
+        const bool sp = t.spin[h] != 0;
+        const int64_t w = t.Ece[ih] + (sp ? t.Acce[ih] + t.epce[ih] : t.epce[ih]);
+        n_hpp += rce * 2 * w;
+        if (rce > 0) q_hpp += t.q[ih] + (sp ? t.qa[ih] : 0);
       }
     }
-    put_feat(row, 21, fratio(q21, kQ));
-    put_feat(row, 22, fratio(q22, kQ));
-    put_feat(row, 23, fratio(n_carry, D));
-    put_feat(row, 24, fratio(q24, kQ));
-    put_feat(row, 25, fratio(n25, C));
-    put_feat(row, 26, fratio(n_bp, D));
-    put_feat(row, 27, fratio(n_bs, D));
-    put_feat(row, 28, fratio(m28, D));
-    put_feat(row, 29, fratio(n29, C));
-    put_feat(row, 30, fratio(n_hpp, D));
-    put_feat(row, 31, fratio(q_hpp, kQ));
-    // accelerators
-    int64_t n_acc = 0, q33 = 0, n_bacc = 0;
-    int n36 = 0, f37 = 0;
-    double f35 = 0.0;
-    for (int a = 0; a < NA; ++a) {
-      if (!((uses >> a) & 1u)) continue;
-      const int lev = t.level[c * NAm + a];
-      int64_t hpA = 0, bacc = 0;
-      for (int h = 0; h < C; ++h) {
-        const int ih = h * NAm + a;
-        if (t.rank[h] < rho) {
-          hpA += t.Ahat[ih];
-          q33 += t.qA[ih];
-          n36 += t.dca[ih] > 0;
-          f37 |= t.Ahat[ih] > 0;
-        } else if (t.rank[h] > rho && t.dca[ih] > 0 && t.level[ih] == lev) {
-          bacc = t.Amax[ih] > bacc ? t.Amax[ih] : bacc;
-        }
-      }
-      n_acc += 2 * (int64_t)t.nra[c * NAm + a] * hpA;
-      n_bacc += (int64_t)t.dca[c * NAm + a] * bacc;
-      const double lv = fratio(lev, b.buckets[a0 + a]);
-      f35 = lv > f35 ? lv : f35;
-    }
-    put_feat(row, 32, fratio(n_acc, D));
-    put_feat(row, 33, fratio(q33, kQ));
-    put_feat(row, 34, fratio(n_bacc, D));
-    put_feat(row, 35, f35);
-    put_feat(row, 36, fratio(n36, C));
-    put_feat(row, 37, f37 ? 1.0 : 0.0);
-    put_feat(row, 38, fratio(sum_q, (int64_t)X * kQ));
-    put_feat(row, 39, fratio(max_qe, kQ));
-    put_feat(row, 40, fratio(sum_qA, kQ));
-    put_feat(row, 41, fratio(C, 256));
-    put_feat(row, 42, fratio(X, 8));
-    put_feat(row, 43, fratio(NA, 8));
-    put_feat(row, 44, fratio(Tmin, T));
-    const int64_t n_est = own + n_carry + n_bs + n_hpp + n_acc + n_bacc;
-    const int64_t q_est = q21 + q22 + q_hpp + q33;
-    put_feat(row, 45, fratio(n_est, D));
-    put_feat(row, 46, fratio(n_est, D) + fratio(q_est, kQ));
-    put_feat(row, 47, fratio(t.Ec[c] + t.Acc[c], sum_dem));
   }
-  return true;
+  put_feat(row, 21, fratio(q21, kQ));
+  put_feat(row, 22, fratio(q22, kQ));
+  put_feat(row, 23, fratio(n_carry, D));
+  put_feat(row, 24, fratio(q24, kQ));
+  put_feat(row, 25, fratio(n25, C));
+  put_feat(row, 26, fratio(n_bp, D));
+  put_feat(row, 27, fratio(n_bs, D));
+  put_feat(row, 28, fratio(m28, D));
+  put_feat(row, 29, fratio(n29, C));
+  put_feat(row, 30, fratio(n_hpp, D));
+  put_feat(row, 31, fratio(q_hpp, kQ));
+  // accelerators
+  int64_t n_acc = 0, q33 = 0, n_bacc = 0;
+  int n36 = 0, f37 = 0;
+  double f35 = 0.0;
+  for (int a = 0; a < NA; ++a) {
+    if (!((uses >> a) & 1u)) continue;
+    const int lev = lv[c * NAm + a];
+    int64_t hpA = 0, bacc = 0;
+    for (int h = 0; h < C; ++h) {
+      const int ih = h * NAm + a;
+      const int rh = rk[h];
+      if (rh < rho) {
+        hpA += t.Ahat[ih];
+        q33 += t.qA[ih];
+        n36 += t.dca[ih] > 0;
+        f37 |= t.Ahat[ih] > 0;
+      } else if (rh > rho && t.dca[ih] > 0 && lv[ih] == lev) {
+        bacc = t.Amax[ih] > bacc ? t.Amax[ih] : bacc;
+      }
+    }
+    n_acc += 2 * (int64_t)t.nra[c * NAm + a] * hpA;
+    n_bacc += (int64_t)t.dca[c * NAm + a] * bacc;
+    const double lvr = fratio(lev, b.buckets[a0 + a]);
+    f35 = lvr > f35 ? lvr : f35;
+  }
+  put_feat(row, 32, fratio(n_acc, D));
+  put_feat(row, 33, fratio(q33, kQ));
+  put_feat(row, 34, fratio(n_bacc, D));
+  put_feat(row, 35, f35);
+  put_feat(row, 36, fratio(n36, C));
+  put_feat(row, 37, f37 ? 1.0 : 0.0);
+  put_feat(row, 38, fratio(t.setv[0], (int64_t)X * kQ));
+  put_feat(row, 39, fratio(t.setv[4], kQ));
+  put_feat(row, 40, fratio(t.setv[1], kQ));
+  put_feat(row, 41, fratio(C, 256));
+  put_feat(row, 42, fratio(X, 8));
+  put_feat(row, 43, fratio(NA, 8));
+  put_feat(row, 44, fratio(t.setv[3], T));
+  const int64_t n_est = own + n_carry + n_bs + n_hpp + n_acc + n_bacc;
+  const int64_t q_est = q21 + q22 + q_hpp + q33;
+  put_feat(row, 45, fratio(n_est, D));
+  put_feat(row, 46, fratio(n_est, D) + fratio(q_est, kQ));
+  put_feat(row, 47, fratio(t.Ec[c] + t.Acc[c], t.setv[2]));
 }
 
 // Work item i: explicit pairs (one candidate each), or in range mode a run of
-// up to 64 consecutive candidates of one set.
+// up to 64 consecutive candidates of one set.  Tables in LDS (kLds) or in the
+// wave's global scratch.
+template <bool kLds>
 __global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
-  unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
-  const int NAm = L.b.max_NA > 0 ? L.b.max_NA : 1;
-  FeatTables t = carve_feat(wbase, L.b.max_C, L.b.max_X, NAm);
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  unsigned char *base = kLds ? lds_raw : L.scratch + (size_t)blockIdx.x * L.scratch_stride;
+  const int NAmx = L.b.max_NA > 0 ? L.b.max_NA : 1;
+  FeatTables t = carve_feat(base, L.b.max_C, L.b.max_X, NAmx);
+  const int lane = threadIdx.x;
   // grid-stride: the item index is wave-uniform by construction
   for (int64_t i = blockIdx.x; i < L.n_items; i += gridDim.x) {
     int64_t set, k0, n_k, out0;
@@ -376,7 +388,7 @@ __global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
       out0 = (int64_t)i;
       if (set < 0 || set >= L.b.n_sets || k0 < 0 || k0 > 0x7FFFFFFF || uu < 0 ||
           uu > 0x7FFFFFFF) {
-        if (threadIdx.x == 0) L.count[i] = -1;
+        if (lane == 0) L.count[i] = -1;
         continue;
       }
       u = (int32_t)uu;
@@ -390,20 +402,61 @@ __global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
     }
     const int64_t c0 = L.b.set_chain_off[set];
     const int C = (int)(L.b.set_chain_off[set + 1] - c0);
+    const int64_t a0 = L.b.set_accel_off[set];
+    const int NA = (int)(L.b.set_accel_off[set + 1] - a0);
+    const int NAm = NA > 0 ? NA : 1;
     feat_build(L.b, set, u, t);
-    for (int c = threadIdx.x; c < C; c += kWave) {
+    if (t.setv[5] >= ((int64_t)1 << 40)) {
+      // integer numerators could overflow: no features for this set
+      for (int64_t k = lane; k < n_k; k += kWave) L.count[out0 + k] = -2;
+      continue;
+    }
+    for (int c = lane; c < C; c += kWave) {
       const int r = L.b.rank0[c0 + c];
       t.order[r] = c;
       t.rank[c] = (int16_t)r;
     }
     __syncthreads();
+    int G = C <= 64 ? 64 / C : 1;
+    G = G < kMaxGroup ? G : kMaxGroup;
     int64_t cur = 0;
-    for (int64_t k = k0; k < k0 + n_k; ++k) {
-      walk_order(t.order, t.rank, C, L.seed, set, cur, k, t.buf);
-      cur = k;
-      const int64_t o = out0 + (k - k0);
-      const bool ok = feat_candidate(L.b, set, t, L.feat + (size_t)o * L.row_stride * 48);
-      if (threadIdx.x == 0) L.count[o] = ok ? C : -2;
+    for (int64_t kb = k0; kb < k0 + n_k; kb += G) {
+      const int ng = (int)(k0 + n_k - kb < G ? k0 + n_k - kb : G);
+      // ranks of the group's candidates
+      for (int j = 0; j < ng; ++j) {
+        walk_order(t.order, t.rank, C, L.seed, set, cur, kb + j, t.buf);
+        cur = kb + j;
+        for (int c = lane; c < C; c += kWave) t.rankg[j * C + c] = t.rank[c];
+        __syncthreads();
+      }
+      // bucket levels (Sec. IV-C) of every (candidate, chain, accelerator)
+      for (int idx = lane; idx < ng * C; idx += kWave) {
+        const int g = idx / C, c = idx - g * C;
+        const int16_t *rk = t.rankg + g * C;
+        const int rho = rk[c];
+        for (int a = 0; a < NA; ++a) {
+          int lev = -1;
+          if (t.dca[c * NAm + a] > 0) {
+            int r = 0, m = 0;
+            for (int h = 0; h < C; ++h) {
+              if (t.dca[h * NAm + a] > 0) {
+                ++m;
+                r += rk[h] < rho ? 1 : 0;
+              }
+            }
+            lev = (int)(((int64_t)r * L.b.buckets[a0 + a]) / m);
+          }
+          t.levelg[(g * C + c) * NAm + a] = lev;
+        }
+      }
+      __syncthreads();
+      for (int idx = lane; idx < ng * C; idx += kWave) {
+        const int g = idx / C, c = idx - g * C;
+        const int64_t o = out0 + (kb - k0) + g;
+        feat_chain(L.b, set, t, t.rankg + g * C, t.levelg + g * C * NAm, c,
+                   L.feat + ((size_t)o * L.row_stride + c) * 48);
+      }
+      for (int g = lane; g < ng; g += kWave) L.count[out0 + (kb - k0) + g] = C;
       __syncthreads();
     }
   }
@@ -449,97 +502,128 @@ __device__ __forceinline__ bf16x8 load_x8(const uint16_t *row, int k0, bool vali
   return load8(row + k0);
 }
 
-// One wave: 16 candidates (rows of layer 2).  Layer 1 runs per candidate in
-// 16-row tiles on the matrix cores (v_mfma_f32_16x16x32_bf16: lane l holds
-// A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16], D[4(l/16)+j][l%16]); the ReLU
-// outputs of the valid rows are summed per column into the pool.
-__global__ __launch_bounds__(kWave) void forward_kernel(FwdLaunch L) {
-  __shared__ uint16_t Pq[16][NH + 8];   // pooled vectors (bfloat16) of the 16 candidates
-  const int l = threadIdx.x;
+// Forward pass, one workgroup of four waves per block of 64 candidates
+// (grid-stride over blocks).  v_mfma_f32_16x16x32_bf16 lane layout: lane l
+// holds A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16] and D[4(l/16)+j][l%16].
+// Layer 1: wave w takes candidates 16w..16w+15 of the block, 16 rows at a
+// time, with W1 staged in LDS; the ReLU outputs of the valid rows are summed
+// per column into the pool.  Layer 2: the 64 pooled vectors (bfloat16, LDS)
+// times W2^T, wave w taking output columns 64w..64w+63 for all 64
+// candidates; layer 3 sums w3 * h2 per candidate across the waves in LDS.
+constexpr int kFwdBlock = 64;
+constexpr int kPqStride = NH + 8;  // padded row of the pooled tile (bank spread)
+
+__global__ __launch_bounds__(256) void forward_kernel(FwdLaunch L) {
+  __shared__ __attribute__((aligned(16))) uint16_t W1s[NH * KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Pq[kFwdBlock * kPqStride];
+  __shared__ float ysum[4][kFwdBlock];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
   const int li = l & 15, lg = l >> 4;
-  const int64_t base = (int64_t)blockIdx.x * 16;
-  const uint16_t *W1 = L.packed + PW1, *W2 = L.packed + PW2, *w3 = L.packed + PW3;
+  const uint16_t *W2 = L.packed + PW2, *w3 = L.packed + PW3;
   const float *b1 = L.params + OB1, *b2 = L.params + OB2;
-  for (int m = 0; m < 16; ++m) {
-    const int64_t cand = base + m;
-    float pool[16];
-    for (int nt = 0; nt < 16; ++nt) pool[nt] = 0.0f;
-    int rows = 0;
-    if (cand < L.n) rows = L.count[cand];
-    if (rows < 0) rows = 0;
-    const uint16_t *X = L.feat + (size_t)cand * L.row_stride * NF;
-    for (int r0 = 0; r0 < rows; r0 += 16) {
-      const int r = r0 + li;
-      const bool rv = r < rows;
-      const bf16x8 a0 = load_x8(X + (size_t)r * NF, 8 * lg, rv);
-      const bf16x8 a1 = load_x8(X + (size_t)r * NF, 32 + 8 * lg, rv);
-      for (int nt = 0; nt < 16; ++nt) {
-        const int n = nt * 16 + li;
-        const bf16x8 bb0 = load8(W1 + (size_t)n * KP + 8 * lg);
-        const bf16x8 bb1 = load8(W1 + (size_t)n * KP + 32 + 8 * lg);
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
-        const float bias = b1[n];
-        float s = 0.0f;
-        for (int j = 0; j < 4; ++j) {
-          const int rr = r0 + 4 * lg + j;
-          const float z = acc[j] + bias;
-          s += (rr < rows && z > 0.0f) ? z : 0.0f;
-        }
-        pool[nt] += s;
-      }
-    }
-    // column sums across the four row groups, then the mean
-    for (int nt = 0; nt < 16; ++nt) {
-      float s = pool[nt];
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
-      const float p = rows > 0 ? s / (float)rows : 0.0f;
-      if (lg == 0) Pq[m][nt * 16 + li] = bf16_rne(p);
-    }
+  {
+    const uint4 *src = reinterpret_cast<const uint4 *>(L.packed + PW1);
+    uint4 *dst = reinterpret_cast<uint4 *>(W1s);
+    for (int i = tid; i < NH * KP / 8; i += 256) dst[i] = src[i];
   }
+  float bias1[16];
+  for (int nt = 0; nt < 16; ++nt) bias1[nt] = b1[nt * 16 + li];
+  const int64_t nblocks = (L.n + kFwdBlock - 1) / kFwdBlock;
   __syncthreads();
-  // layer 2 on the 16 pooled vectors: A = Pq (16 x 256), B = W2^T
-  float ypart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int nt = 0; nt < 16; ++nt) {
-    const int n = nt * 16 + li;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int kk = 0; kk < NH; kk += 32) {
-      const bf16x8 a = load8(&Pq[li][kk + 8 * lg]);
-      const bf16x8 bb = load8(W2 + (size_t)n * NH + kk + 8 * lg);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
-    }
-    const float bias = b2[n];
-    const float w = bf16_value(w3[n]);
-    for (int j = 0; j < 4; ++j) {
-      const int m = 4 * lg + j;
-      const float z = acc[j] + bias;
-      const uint16_t hq = bf16_rne(z > 0.0f ? z : 0.0f);
-      ypart[j] += w * bf16_value(hq);
-      if (L.act && base + m < L.n) {
-        uint16_t *a = reinterpret_cast<uint16_t *>(L.act) + (size_t)(base + m) * 512;
-        a[256 + n] = hq;
+  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int64_t base = blk * kFwdBlock;
+    // ---- layer 1 and pooling: 16 candidates per wave
+    for (int m = 0; m < 16; ++m) {
+      const int mb = w * 16 + m;
+      const int64_t cand = base + mb;
+      int rows = 0;
+      if (cand < L.n) rows = L.count[cand];
+      rows = rows < 0 ? 0 : rows;
+      const uint16_t *X = L.feat + (size_t)cand * L.row_stride * NF;
+      float pool[16];
+      for (int nt = 0; nt < 16; ++nt) pool[nt] = 0.0f;
+      for (int r0 = 0; r0 < rows; r0 += 16) {
+        const int r = r0 + li;
+        const bool rv = r < rows;
+        const bf16x8 a0 = load_x8(X + (size_t)r * NF, 8 * lg, rv);
+        const bf16x8 a1 = load_x8(X + (size_t)r * NF, 32 + 8 * lg, rv);
+        for (int nt = 0; nt < 16; ++nt) {
+          const int n = nt * 16 + li;
+          const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
+          const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
+          f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
+          float sacc = 0.0f;
+          for (int j = 0; j < 4; ++j) {
+            const int rr = r0 + 4 * lg + j;
+            const float z = acc[j] + bias1[nt];
+            sacc += (rr < rows && z > 0.0f) ? z : 0.0f;
+          }
+          pool[nt] += sacc;
+        }
+      }
+      for (int nt = 0; nt < 16; ++nt) {
+        float sv = pool[nt];
+        sv += __shfl_xor(sv, 16);
+        sv += __shfl_xor(sv, 32);
+        const float p = rows > 0 ? sv / (float)rows : 0.0f;
+        if (lg == 0) Pq[mb * kPqStride + nt * 16 + li] = bf16_rne(p);
       }
     }
-  }
-  // y of candidate 4*lg + j: sum over the 16 lanes of the row group
-  for (int j = 0; j < 4; ++j) {
-    float s = ypart[j];
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
-    s += __shfl_xor(s, 8);
-    const int64_t cand = base + 4 * lg + j;
-    if (li == 0 && cand < L.n) L.out[cand] = s + L.params[OB3];
-  }
-  if (L.act) {
-    for (int m = 0; m < 16; ++m) {
-      const int64_t cand = base + m;
-      if (cand >= L.n) break;
-      uint16_t *a = reinterpret_cast<uint16_t *>(L.act) + (size_t)cand * 512;
-      for (int k = l; k < NH; k += kWave) a[k] = Pq[m][k];
+    __syncthreads();
+    // ---- layer 2 (64 x 256 x 256) and layer 3 partial sums
+    float yp[4][4];
+    for (int mt = 0; mt < 4; ++mt)
+      for (int j = 0; j < 4; ++j) yp[mt][j] = 0.0f;
+    for (int q = 0; q < 4; ++q) {
+      const int n = (w * 4 + q) * 16 + li;
+      f32x4 acc[4];
+      for (int mt = 0; mt < 4; ++mt) acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int kk = 0; kk < NH; kk += 32) {
+        const bf16x8 bb = load8(W2 + (size_t)n * NH + kk + 8 * lg);
+        for (int mt = 0; mt < 4; ++mt) {
+          const bf16x8 a = load8(Pq + (mt * 16 + li) * kPqStride + kk + 8 * lg);
+          acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[mt], 0, 0, 0);
+        }
+      }
+      const float bias = b2[n];
+      const float wv = bf16_value(w3[n]);
+      for (int mt = 0; mt < 4; ++mt) {
+        for (int j = 0; j < 4; ++j) {
+          const int mb = mt * 16 + 4 * lg + j;
+          const float z = acc[mt][j] + bias;
+          const uint16_t hq = bf16_rne(z > 0.0f ? z : 0.0f);
+          yp[mt][j] += wv * bf16_value(hq);
+          if (L.act && base + mb < L.n)
+            reinterpret_cast<uint16_t *>(L.act)[(size_t)(base + mb) * 512 + 256 + n] = hq;
+        }
+      }
     }
+    // sum over the 16 lanes of a row group, then over the four waves
+    for (int mt = 0; mt < 4; ++mt) {
+      for (int j = 0; j < 4; ++j) {
+        float sv = yp[mt][j];
+        sv += __shfl_xor(sv, 1);
+        sv += __shfl_xor(sv, 2);
+        sv += __shfl_xor(sv, 4);
+        sv += __shfl_xor(sv, 8);
+        if (li == 0) ysum[w][mt * 16 + 4 * lg + j] = sv;
+      }
+    }
+    if (L.act) {
+      for (int i = tid; i < kFwdBlock * NH; i += 256) {
+        const int mb = i / NH, k = i - mb * NH;
+        if (base + mb < L.n)
+          reinterpret_cast<uint16_t *>(L.act)[(size_t)(base + mb) * 512 + k] = Pq[mb * kPqStride + k];
+      }
+    }
+    __syncthreads();
+    if (tid < kFwdBlock && base + tid < L.n)
+      L.out[base + tid] = ((ysum[0][tid] + ysum[1][tid]) + (ysum[2][tid] + ysum[3][tid])) +
+                          L.params[OB3];
+    __syncthreads();
   }
 }
 
@@ -668,10 +752,17 @@ size_t feat_wave_bytes(const DevBatch &b) {
   return (feat_table_bytes(b.max_C, b.max_X, NAm) + 255) & ~(size_t)255;
 }
 
+bool feat_in_lds(const DevBatch &b) { return feat_wave_bytes(b) <= kFeatLdsMax; }
+
 int launch_features(const FeatLaunch &L, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (L.n_items == 0) return 0;
-  hipLaunchKernelGGL(features_kernel, dim3(L.grid), dim3(kWave), 0, st, L);
+  if (feat_in_lds(L.b)) {
+    hipLaunchKernelGGL(features_kernel<true>, dim3(L.grid), dim3(kWave), feat_wave_bytes(L.b), st,
+                       L);
+  } else {
+    hipLaunchKernelGGL(features_kernel<false>, dim3(L.grid), dim3(kWave), 0, st, L);
+  }
   return (int)hipGetLastError();
 }
 
@@ -683,9 +774,9 @@ int launch_pack(const float *params, uint16_t *packed, void *stream) {
 
 int launch_forward(const FwdLaunch &L, void *stream) {
   if (L.n == 0) return 0;
-  const int64_t blocks = (L.n + 15) / 16;
-  hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kWave), 0, (hipStream_t)stream,
-                     L);
+  const int64_t blocks = (L.n + kFwdBlock - 1) / kFwdBlock;
+  const int64_t grid = blocks < 4096 ? blocks : 4096;  // persistent: 16 workgroups per CU at most
+  hipLaunchKernelGGL(forward_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, L);
   return (int)hipGetLastError();
 }
 

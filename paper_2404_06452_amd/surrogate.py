@@ -16,6 +16,21 @@ import numpy as np
 from . import _paam
 
 
+# Training recipe: sets of the utilisation-sweep generator (4-64 chains x 2-12
+# callbacks, 4 executors) analysed at a utilisation scale drawn log-uniformly
+# over 0.2-10 % of their U = 1 draw, so that the targets span the feasibility
+# boundary (at the sweep's own levels 0.10-0.95 almost every candidate's
+# largest R/D exceeds 2 and the target is constant); candidates k uniform over
+# the walk's first 256; target min(max R/D, 2).
+TRAIN_UTIL = (2, 100)
+TRAIN_CAP = 2
+
+
+def recipe_pairs(n_sets: int, n_samples: int, seed: int, n_cand: int = 256):
+    from . import chaingen
+    return chaingen.training_triples(n_sets, n_samples, n_cand, TRAIN_UTIL, seed)
+
+
 class Trainer:
     """Mean-squared-error training of the ranking network on (set, k,
     util_permille) pairs of one uploaded batch."""
@@ -35,7 +50,7 @@ class Trainer:
         self.fws = _paam.workspace(_paam.paam_features_bytes(dev, batch), d)
         self.bws = _paam.workspace(_paam.paam_mlp_backward_bytes(batch), d)
 
-    def targets(self, pairs, cap_mult: int = 2):
+    def targets(self, pairs, cap_mult: int = TRAIN_CAP):
         """Exact-analysis targets of device pairs [n, 3]: float32 ratios."""
         o = _paam.wcrt_opts(cap_mult=cap_mult, full=True)
         n = int(pairs.shape[0])
@@ -78,14 +93,14 @@ class Trainer:
         learning rate decays linearly to lr_final.  Returns the mean loss of
         every epoch."""
         import torch
+
+        from . import chaingen
         n = int(pairs.shape[0])
-        g = torch.Generator(device="cpu")
-        g.manual_seed(order_seed)
         steps = epochs * ((n + self.batch - 1) // self.batch)
         k = 0
         losses = []
         for ep in range(epochs):
-            perm = torch.randperm(n, generator=g).to(pairs.device)
+            perm = torch.from_numpy(chaingen.shuffle_order(n, order_seed + ep)).to(pairs.device)
             acc = torch.zeros(1, dtype=torch.float64, device=pairs.device)
             t0 = time.perf_counter()
             nb = 0
