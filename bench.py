@@ -44,18 +44,19 @@ def log(msg):
 # workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled
 # by the counters' reading for the 1 GiB calibration copy.  Valid only for the
 # kernel source with this SHA-256; reported as null for any other.
-TRAFFIC = {"sha256": "79dacb323eb31a7063da12404526ee880d8608e813a2da7640c734d838e65e32",
-           "bytes_per_launch": 38.66e9, "sets": 1_000_000}
+TRAFFIC = {"sha256": "5139d23105e9a3d138665b1160059149b61d82c6cf0b91a0c6c4caf0342b9172",
+           "bytes_per_launch": 41.76e9, "sets": 1_000_000, "waves_per_cu": 12}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
 
 
-def measured_traffic(n_sets):
+def measured_traffic(n_sets, waves_per_cu):
     import hashlib
     with open(KERNEL_SRC, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if sha != TRAFFIC["sha256"] or n_sets != TRAFFIC["sets"]:
+    if (sha != TRAFFIC["sha256"] or n_sets != TRAFFIC["sets"]
+            or waves_per_cu != TRAFFIC["waves_per_cu"]):
         return None
     return TRAFFIC["bytes_per_launch"]
 
@@ -236,10 +237,24 @@ def main():
     stream = torch.cuda.Stream()
     copy_gbs = copy_calibration(torch, stream)
     log("plain device copy: %.0f GB/s (read + write)" % copy_gbs)
-    opts = [_paam.wcrt_opts(full=True, util_permille=u, waves_per_cu=args.waves_per_cu)
-            for u in levels]
-    ws = _paam.workspace(max(_paam.paam_wcrt_bytes(dev, o) for o in opts))
     outs = [_paam.WcrtOut(dev, True) for _ in levels]
+    tune = None
+    wpc = args.waves_per_cu
+    if wpc == 0:
+        # schedule autotuner (library): persistent waves per CU, timed on the
+        # middle level of the sweep
+        cands = [4, 6, 8, 10, 12, 16]
+        t_opts = _paam.wcrt_opts(full=True, util_permille=levels[len(levels) // 2])
+        ws_t = _paam.workspace(_paam.paam_wcrt_bytes(
+            dev, _paam.wcrt_opts(full=True, waves_per_cu=max(cands))))
+        best_ms = _paam.paam_wcrt_autotune(dev, t_opts, cands, 1, outs[0], ws_t, stream)
+        wpc = int(t_opts.waves_per_cu)
+        tune = {"candidates_waves_per_cu": cands, "chosen": wpc, "best_ms": best_ms,
+                "level": levels[len(levels) // 2] / 1000}
+        log("autotune: %d waves per CU (%.1f ms per launch)" % (wpc, best_ms))
+        del ws_t
+    opts = [_paam.wcrt_opts(full=True, util_permille=u, waves_per_cu=wpc) for u in levels]
+    ws = _paam.workspace(max(_paam.paam_wcrt_bytes(dev, o) for o in opts))
 
     def sweep(s):
         for o, out in zip(opts, outs):
@@ -342,6 +357,7 @@ def main():
             "n_sets": cs.n_sets, "levels": len(levels), "analyses_per_step": analyses,
             "chains": cs.n_chains, "callbacks": cs.n_callbacks, "segments": cs.n_segments,
             "subchains": dev.n_subchains, "hip_graph": graph is not None,
+            "waves_per_cu": wpc, "autotune": tune,
             "parallelism": "single GPU",
         },
         "parity": {"sampled_analyses": n_s * len(levels), "mismatches": mism,
@@ -354,7 +370,7 @@ def main():
             "peak": PEAK_TERMS / 1e9,
             "unit": "Gterm/s",
             "frac": achieved / PEAK_TERMS,
-            "traffic": measured_traffic(cs.n_sets),
+            "traffic": measured_traffic(cs.n_sets, wpc),
             "kernel": "wcrt_kernel",
             "avg_launch_ms": launch_ms,
             "copy_GBps_measured": copy_gbs,

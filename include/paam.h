@@ -121,6 +121,17 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
                             int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R, void *d_ws,
                             size_t ws_bytes, paam_stream stream);
 
+/* Schedule autotuner: runs paam_wcrt_batch on this batch with o->waves_per_cu
+ * set to each of the n_cand values in cand (1..32), reps times each, timed
+ * with HIP events on the stream, and writes the fastest value into
+ * o->waves_per_cu and its mean time per launch (ms) into *best_ms.  Outputs
+ * and workspace as for paam_wcrt_batch; the workspace must hold the largest
+ * candidate's paam_wcrt_bytes.  Blocks until the timing runs have finished. */
+paam_status paam_wcrt_autotune(const paam_chainset *cs, paam_wcrt_opts *o, const int32_t *cand,
+                               int32_t n_cand, int32_t reps, int8_t *set_sched,
+                               int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R,
+                               void *d_ws, size_t ws_bytes, paam_stream stream, float *best_ms);
+
 /* ---------------- priority-order search (candidate orders) ----------------
  * Candidate 0 of a set is its uploaded order (chains by decreasing prio).
  * Candidate k >= 1 is candidate k-1 with two positions swapped: with u1, u2

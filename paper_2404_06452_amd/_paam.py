@@ -22,8 +22,8 @@ PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
 
 EXPORTED = (
     "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
-    "paam_wcrt_bytes", "paam_wcrt_batch", "paam_search_bytes", "paam_priority_search",
-    "paam_candidate_bytes", "paam_candidate_wcrt", "paam_features_bytes", "paam_features",
+    "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_autotune", "paam_search_bytes",
+    "paam_priority_search", "paam_candidate_bytes", "paam_candidate_wcrt", "paam_features_bytes", "paam_features",
     "paam_mlp_pack", "paam_mlp_forward", "paam_mlp_backward_bytes", "paam_mlp_backward",
     "paam_mlp_adam_step", "paam_score_bytes", "paam_score_candidates",
     "paam_last_error", "paam_version",
@@ -75,6 +75,10 @@ def lib():
         L.paam_chainset_info.argtypes = [P, P]
         L.paam_wcrt_bytes.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), ctypes.POINTER(S)]
         L.paam_wcrt_batch.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P, S, P]
+        L.paam_wcrt_autotune.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, ctypes.c_int32,
+                                          ctypes.c_int32, P, P, P, P, P, S, P,
+                                          ctypes.POINTER(ctypes.c_float)]
+        L.paam_wcrt_autotune.restype = ctypes.c_int32
         L.paam_search_bytes.argtypes = [P, ctypes.POINTER(paam_search_opts), ctypes.POINTER(S)]
         L.paam_priority_search.argtypes = [P, ctypes.POINTER(paam_search_opts), P, P, P, P, S, P]
         I64, I32, U64, F = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_float
@@ -207,6 +211,21 @@ def paam_wcrt_batch(cs: Chainset, opts: paam_wcrt_opts, out: WcrtOut, ws, stream
                                 _dev_ptr(out.chain_R), ws.data_ptr(), ws.numel(),
                                 _stream_ptr(stream)),
           "paam_wcrt_batch")
+
+
+def paam_wcrt_autotune(cs: Chainset, opts: paam_wcrt_opts, candidates, reps: int, out: WcrtOut,
+                       ws, stream=None) -> float:
+    """Sets opts.waves_per_cu to the fastest of the candidates; returns its
+    mean launch time in ms."""
+    cand = np.ascontiguousarray(candidates, np.int32)
+    best = ctypes.c_float(0.0)
+    check(lib().paam_wcrt_autotune(cs.handle, ctypes.byref(opts), cand.ctypes.data, len(cand), reps,
+                                   out.set_sched.data_ptr(), out.set_worst.data_ptr(),
+                                   out.set_worst_R.data_ptr(), _dev_ptr(out.chain_R),
+                                   ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                                   ctypes.byref(best)),
+          "paam_wcrt_autotune")
+    return float(best.value)
 
 
 def workspace(nbytes: int, device="cuda:0"):

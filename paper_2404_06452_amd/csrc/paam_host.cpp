@@ -617,6 +617,57 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
   return PAAM_OK;
 }
 
+paam_status paam_wcrt_autotune(const paam_chainset *cs, paam_wcrt_opts *o, const int32_t *cand,
+                               int32_t n_cand, int32_t reps, int8_t *set_sched,
+                               int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R,
+                               void *d_ws, size_t ws_bytes, paam_stream stream, float *best_ms) {
+  if (!cs || !o || !cand || !best_ms) return fail(PAAM_E_INVAL, "null argument");
+  if (n_cand < 1 || n_cand > 64 || reps < 1 || reps > 100)
+    return fail(PAAM_E_INVAL, "need 1 <= n_cand <= 64 and 1 <= reps <= 100");
+  for (int i = 0; i < n_cand; ++i)
+    if (cand[i] < 1 || cand[i] > 32) return fail(PAAM_E_INVAL, "candidate waves_per_cu outside 1..32");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(he, "hipEventCreate");
+  }
+  paam_status st_out = PAAM_OK;
+  float best = 0.0f;
+  int32_t best_w = -1;
+  paam_wcrt_opts t = *o;
+  for (int i = 0; i < n_cand && st_out == PAAM_OK; ++i) {
+    t.waves_per_cu = cand[i];
+    // one untimed launch, then reps timed ones
+    st_out = paam_wcrt_batch(cs, &t, set_sched, set_worst, set_worst_R, chain_R, d_ws, ws_bytes,
+                             stream);
+    if (st_out != PAAM_OK) break;
+    he = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && st_out == PAAM_OK && he == hipSuccess; ++r)
+      st_out = paam_wcrt_batch(cs, &t, set_sched, set_worst, set_worst_R, chain_R, d_ws, ws_bytes,
+                               stream);
+    if (he == hipSuccess) he = hipEventRecord(e1, st);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess && st_out == PAAM_OK) st_out = hip_fail(he, "autotune timing");
+    if (st_out != PAAM_OK) break;
+    ms /= (float)reps;
+    if (best_w < 0 || ms < best) {
+      best = ms;
+      best_w = cand[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st_out != PAAM_OK) return st_out;
+  o->waves_per_cu = best_w;
+  *best_ms = best;
+  return PAAM_OK;
+}
+
 static paam_status check_search(const paam_chainset *cs, const paam_search_opts *o) {
   if (!cs || !o) return fail(PAAM_E_INVAL, "null argument");
   paam_status st = check_opts(&o->wcrt);

@@ -140,3 +140,20 @@ def test_repeatable_and_schedule_independent(paam):
         g = paam.wcrt(dev, full=True, util_permille=400, waves_per_cu=w)
         for k in ref:
             assert np.array_equal(ref[k], g[k]), (w, k)
+
+
+def test_autotune_picks_a_candidate_and_keeps_results():
+    import torch
+
+    from paper_2404_06452_amd import _paam
+    cs = chaingen.generate("sweep", 300)
+    dev = _paam.Chainset(cs, device="cuda:0")
+    o = _paam.wcrt_opts(full=True, util_permille=300)
+    out = _paam.WcrtOut(dev, True)
+    ws = _paam.workspace(_paam.paam_wcrt_bytes(dev, _paam.wcrt_opts(full=True, waves_per_cu=8)))
+    ms = _paam.paam_wcrt_autotune(dev, o, [2, 4, 8], 2, out, ws)
+    torch.cuda.synchronize()
+    assert o.waves_per_cu in (2, 4, 8) and ms > 0
+    r = oracle.wcrt(cs, full=True, util_permille=300)
+    assert np.array_equal(out.chain_R.cpu().numpy()[:cs.n_chains], r["chain_R"])
+    assert np.array_equal(out.set_sched.cpu().numpy(), r["sched"])
