@@ -73,6 +73,7 @@ struct Plan {
   std::vector<int32_t> buckets;
   std::vector<int64_t> work_order;
   int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0;
+  std::vector<paam::SizeClass> classes;
   int64_t max_tot = 0;
 };
 
@@ -341,10 +342,37 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     for (int64_t s = lo; s < hi; ++s) fill_set(h, s, P);
     return PAAM_OK;
   });
+  // work order: by size class (chain count up to 16, 32, 64, ...), then by
+  // decreasing estimated cost within a class
+  auto size_class = [&](int64_t s) {
+    const int C = (int)(h->set_chain_off[s + 1] - h->set_chain_off[s]);
+    int k = 0;
+    while ((16 << k) < C) ++k;
+    return k;
+  };
   P.work_order.resize(S);
   std::iota(P.work_order.begin(), P.work_order.end(), 0);
-  std::stable_sort(P.work_order.begin(), P.work_order.end(),
-                   [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+  std::stable_sort(P.work_order.begin(), P.work_order.end(), [&](int64_t a, int64_t b) {
+    const int ka = size_class(a), kb = size_class(b);
+    if (ka != kb) return ka < kb;
+    return cost[a] > cost[b];
+  });
+  for (int64_t i = 0; i < S; ++i) {
+    const int64_t s = P.work_order[i];
+    const int k = size_class(s);
+    if (P.classes.empty() || size_class(P.work_order[P.classes.back().begin]) != k)
+      P.classes.push_back(paam::SizeClass{i, 0, 0, 0, 0, 1, 1});
+    paam::SizeClass &c = P.classes.back();
+    const int64_t c0 = h->set_chain_off[s];
+    const int C = (int)(h->set_chain_off[s + 1] - c0);
+    const int64_t cb0 = h->chain_cb_off[c0], cb1 = h->chain_cb_off[c0 + C];
+    c.count += 1;
+    c.max_C = std::max(c.max_C, C);
+    c.max_X = std::max(c.max_X, (int32_t)(h->set_exec_off[s + 1] - h->set_exec_off[s]));
+    c.max_NA = std::max(c.max_NA, (int32_t)(h->set_accel_off[s + 1] - h->set_accel_off[s]));
+    c.max_runs = std::max(c.max_runs, nrun[s]);
+    c.max_segs = std::max(c.max_segs, (int32_t)(h->cb_seg_off[cb1] - h->cb_seg_off[cb0]));
+  }
   return PAAM_OK;
 }
 
@@ -535,6 +563,8 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   cs->n_exec = P.n_exec;
   cs->n_accel = P.n_accel;
   cs->max_tot = P.max_tot;
+  cs->n_classes = (int)P.classes.size();
+  for (int k = 0; k < cs->n_classes; ++k) cs->cls[k] = P.classes[k];
   *out = cs;
   return PAAM_OK;
 }
@@ -568,10 +598,25 @@ static paam_status check_opts(const paam_wcrt_opts *o) {
   return PAAM_OK;
 }
 
-static int grid_for(const paam_chainset *cs, const paam_wcrt_opts *o) {
+// The batch restricted to one size class: its slice of the work order and
+// its maxima (set indices stay global).
+static paam::DevBatch class_view(const paam_chainset *cs, int k) {
+  paam::DevBatch b = cs->dev;
+  const paam::SizeClass &c = cs->cls[k];
+  b.work_order = cs->dev.work_order + c.begin;
+  b.n_sets = c.count;
+  b.max_C = c.max_C;
+  b.max_X = c.max_X;
+  b.max_NA = c.max_NA;
+  b.max_runs = std::max(c.max_runs, 1);
+  b.max_segs = std::max(c.max_segs, 1);
+  return b;
+}
+
+static int grid_n(int64_t n_sets, const paam_wcrt_opts *o) {
   int w = o->waves_per_cu > 0 ? o->waves_per_cu : 8;
   int64_t g = (int64_t)num_cus() * w;
-  if (g > cs->dev.n_sets) g = cs->dev.n_sets;
+  if (g > n_sets) g = n_sets;
   return (int)std::max<int64_t>(g, 1);
 }
 
@@ -579,7 +624,12 @@ paam_status paam_wcrt_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, si
   if (!cs || !ws_bytes) return fail(PAAM_E_INVAL, "null argument");
   paam_status st = check_opts(o);
   if (st != PAAM_OK) return st;
-  *ws_bytes = 256 + (size_t)grid_for(cs, o) * paam::wave_scratch_bytes(cs->dev);
+  size_t need = 256;
+  for (int k = 0; k < cs->n_classes; ++k) {
+    const paam::DevBatch b = class_view(cs, k);
+    need = std::max(need, 256 + (size_t)grid_n(b.n_sets, o) * paam::wave_scratch_bytes(b));
+  }
+  *ws_bytes = need;
   return PAAM_OK;
 }
 
@@ -598,22 +648,26 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
     return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
   if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
     return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
-  paam::WcrtLaunch L;
-  L.b = cs->dev;
-  L.o = *o;
-  L.set_sched = set_sched;
-  L.set_worst = set_worst;
-  L.set_worst_R = set_worst_R;
-  L.chain_R = o->full ? chain_R : nullptr;
-  L.counter = static_cast<unsigned long long *>(d_ws);
-  L.scratch = static_cast<unsigned char *>(d_ws) + 256;
-  L.scratch_stride = paam::wave_scratch_bytes(cs->dev);
-  L.lds_bytes = paam::wave_lds_bytes(cs->dev);
-  L.grid = grid_for(cs, o);
-  if (L.lds_bytes > 160 * 1024)
-    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)", L.lds_bytes);
-  int e = paam::launch_wcrt(L, stream);
-  if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
+  if (paam::wave_lds_bytes(cs->dev) > 160 * 1024)
+    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
+                paam::wave_lds_bytes(cs->dev));
+  // one launch per size class, in stream order on the same workspace
+  for (int k = 0; k < cs->n_classes; ++k) {
+    paam::WcrtLaunch L;
+    L.b = class_view(cs, k);
+    L.o = *o;
+    L.set_sched = set_sched;
+    L.set_worst = set_worst;
+    L.set_worst_R = set_worst_R;
+    L.chain_R = o->full ? chain_R : nullptr;
+    L.counter = static_cast<unsigned long long *>(d_ws);
+    L.scratch = static_cast<unsigned char *>(d_ws) + 256;
+    L.scratch_stride = paam::wave_scratch_bytes(L.b);
+    L.lds_bytes = paam::wave_lds_bytes(L.b);
+    L.grid = grid_n(L.b.n_sets, o);
+    int e = paam::launch_wcrt(L, stream);
+    if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
+  }
   return PAAM_OK;
 }
 
@@ -686,7 +740,12 @@ paam_status paam_search_bytes(const paam_chainset *cs, const paam_search_opts *o
   if (!ws_bytes) return fail(PAAM_E_INVAL, "null argument");
   paam_status st = check_search(cs, o);
   if (st != PAAM_OK) return st;
-  *ws_bytes = 256 + (size_t)grid_for(cs, &o->wcrt) * paam::wave_search_bytes(cs->dev);
+  size_t need = 256;
+  for (int k = 0; k < cs->n_classes; ++k) {
+    const paam::DevBatch b = class_view(cs, k);
+    need = std::max(need, 256 + (size_t)grid_n(b.n_sets, &o->wcrt) * paam::wave_search_bytes(b));
+  }
+  *ws_bytes = need;
   return PAAM_OK;
 }
 
@@ -702,22 +761,25 @@ paam_status paam_priority_search(const paam_chainset *cs, const paam_search_opts
     return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
   if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
     return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
-  paam::SearchLaunch L;
-  L.b = cs->dev;
-  L.o = *o;
-  L.found = found;
-  L.n_exact = n_exact;
-  L.found_prio = found_prio;
-  L.counter = static_cast<unsigned long long *>(d_ws);
-  L.scratch = static_cast<unsigned char *>(d_ws) + 256;
-  L.scratch_stride = paam::wave_search_bytes(cs->dev);
-  L.analysis_stride = paam::wave_scratch_bytes(cs->dev);
-  L.lds_bytes = paam::wave_lds_bytes(cs->dev);
-  L.grid = grid_for(cs, &o->wcrt);
-  if (L.lds_bytes > 160 * 1024)
-    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)", L.lds_bytes);
-  int e = paam::launch_search(L, stream);
-  if (e != 0) return hip_fail((hipError_t)e, "search launch");
+  if (paam::wave_lds_bytes(cs->dev) > 160 * 1024)
+    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
+                paam::wave_lds_bytes(cs->dev));
+  for (int k = 0; k < cs->n_classes; ++k) {
+    paam::SearchLaunch L;
+    L.b = class_view(cs, k);
+    L.o = *o;
+    L.found = found;
+    L.n_exact = n_exact;
+    L.found_prio = found_prio;
+    L.counter = static_cast<unsigned long long *>(d_ws);
+    L.scratch = static_cast<unsigned char *>(d_ws) + 256;
+    L.scratch_stride = paam::wave_search_bytes(L.b);
+    L.analysis_stride = paam::wave_scratch_bytes(L.b);
+    L.lds_bytes = paam::wave_lds_bytes(L.b);
+    L.grid = grid_n(L.b.n_sets, &o->wcrt);
+    int e = paam::launch_search(L, stream);
+    if (e != 0) return hip_fail((hipError_t)e, "search launch");
+  }
   return PAAM_OK;
 }
 

@@ -66,11 +66,26 @@ struct DevBatch {
 
 }  // namespace paam
 
+namespace paam {
+// Sets of one size class (chain count in (limit/2, limit], limit a power of two
+// from 16 up): a contiguous range of the work order and the class's maxima.
+// The analysis and the search launch once per class, so the LDS tables, the
+// per-wave scratch and the occupancy follow the class rather than the
+// batch's largest set.
+struct SizeClass {
+  int64_t begin, count;
+  int32_t max_C, max_X, max_NA, max_runs, max_segs;
+};
+constexpr int kMaxClasses = 12;
+}  // namespace paam
+
 struct paam_chainset {
   paam::DevBatch dev;
   size_t arena_bytes;
   int64_t n_exec, n_accel;
   int64_t max_tot;  // largest total demand of a set: sum of E, A + 2 kappa and epsilon
+  int n_classes;
+  paam::SizeClass cls[paam::kMaxClasses];
 };
 
 namespace paam {
