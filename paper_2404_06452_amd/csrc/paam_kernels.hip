@@ -49,6 +49,11 @@ __device__ __forceinline__ int wave_max_int(int v) {
   return v;
 }
 
+__device__ __forceinline__ int wave_min_int(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
 // R_a / D_a > R_b / D_b for R, D < 2^53 (INF largest), exact in 128 bits.
 __device__ __forceinline__ bool ratio_gt(double Ra, int64_t Da, double Rb, int64_t Db) {
   if (isinf(Ra)) return !isinf(Rb);
@@ -417,13 +422,69 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         r = S.r[s];
       }
       const bool hasP = valid && b.hpx_mask[x0 + e] != 0;
-      const int hend = wave_max_int(valid ? (hasP ? C : rho) : 0);
+      // the loop bound is the same on every lane: keep it in a scalar register
+      const int hend = __builtin_amdgcn_readfirstlane(wave_max_int(valid ? (hasP ? C : rho) : 0));
       const bool needL3 = (inf1 & kNeedL3) != 0;
       const int accm = inf1 & 0xff;
       const double *wp = L.WP + e * C;
       const double *pt = L.Pt + e * C;
       double I0 = 0.0, I1 = 0.0, l3 = 0.0;
       int h = 0;
+      if (NA == 1) {
+        // One accelerator: the Lemma 3 weight of h is Ahat[h] for a lane that
+        // needs Lemma 3 and ranks below h, else 0.  The sub-chains of a chunk
+        // are sorted by rank, so h splits into three ranges: below every
+        // lane's rank (hp weight for all), between the smallest and largest
+        // rank (per-lane selects), above every rank (hpp weight for all).
+        const bool l3on = needL3 && (accm & 1) != 0;
+        const double *ah = L.Ahat;
+        const int rlo = __builtin_amdgcn_readfirstlane(wave_min_int(valid ? rho : C));
+        const int rhi = __builtin_amdgcn_readfirstlane(wave_max_int(valid ? rho : -1));
+        const int e_lo = rlo < hend ? rlo : hend;
+        const int e_mid = rhi + 1 < hend ? rhi + 1 : hend;
+#pragma unroll 2
+        for (; h + 1 < e_lo; h += 2) {
+          const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
+          const double m0 = mu_term(r, q0.x, q0.y);
+          const double m1 = mu_term(r, q1.x, q1.y);
+          const double av0 = ah[h], av1 = ah[h + 1];
+          I0 = fma(m0, wp[h], I0);
+          I1 = fma(m1, wp[h + 1], I1);
+          l3 = fma(m0, l3on ? av0 : 0.0, l3);
+          l3 = fma(m1, l3on ? av1 : 0.0, l3);
+        }
+        if (h < e_lo) {
+          const double2 q0 = L.KR[h];
+          const double m0 = mu_term(r, q0.x, q0.y);
+          const double av0 = ah[h];
+          I0 = fma(m0, wp[h], I0);
+          l3 = fma(m0, l3on ? av0 : 0.0, l3);
+          ++h;
+        }
+        for (; h < e_mid; ++h) {
+          const double2 q0 = L.KR[h];
+          const double m0 = mu_term(r, q0.x, q0.y);
+          double w0 = h < rho ? wp[h] : pt[h];
+          w0 = h == rho ? 0.0 : w0;
+          const double av0 = ah[h];  // h < hend <= C: in bounds
+          I0 = fma(m0, w0, I0);
+          l3 = fma(m0, (l3on && h < rho) ? av0 : 0.0, l3);
+        }
+#pragma unroll 2
+        for (; h + 1 < hend; h += 2) {
+          const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
+          const double m0 = mu_term(r, q0.x, q0.y);
+          const double m1 = mu_term(r, q1.x, q1.y);
+          I0 = fma(m0, pt[h], I0);
+          I1 = fma(m1, pt[h + 1], I1);
+        }
+        if (h < hend) {
+          const double2 q0 = L.KR[h];
+          const double m0 = mu_term(r, q0.x, q0.y);
+          I0 = fma(m0, pt[h], I0);
+          ++h;
+        }
+      }
       for (; h + 1 < hend; h += 2) {
         const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
         const double m0 = mu_term(r, q0.x, q0.y);
