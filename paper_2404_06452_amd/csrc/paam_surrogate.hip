@@ -17,18 +17,27 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ features
 
-// A wave computes the features of up to kMaxGroup consecutive candidates of a
-// set at once: lane g*C + c holds chain c of candidate g (one candidate per
-// pass when C > 64).
+// Two schedules compute identical features.  Sets of up to 64 chains: a wave
+// computes up to kMaxGroup consecutive candidates at once (lane g*C + c holds
+// chain c of candidate g), each lane summing over the other chains directly.
+// Larger sets: one candidate at a time; wave-wide prefix sums and suffix
+// maxima over the rank order give every chain's higher- and lower-priority
+// totals by lookup (O(C (X + NA)) per candidate instead of O(C^2 X)).
 constexpr int kMaxGroup = 16;
+constexpr int kScanC = 64;  // sets with more chains use the prefix-scan schedule
 
 // Per-wave tables: a set's order-independent totals (built once per set), the
-// walk state, and the ranks and bucket levels of the group's candidates.
+// walk state, and the per-candidate ranks, bucket levels and scans.
 struct FeatTables {
   int64_t *Ec, *Acc, *epc, *Emax, *qsum, *qasum, *T, *D;  // [Cm]
   int64_t *Ece, *Acce, *epce, *bl, *bS, *q, *qa;          // [Cm][X]
+  int64_t *hpn, *hpq;                                      // [Cm][X] OS-preemption numerators
   int64_t *Ahat, *Amax, *qA;                               // [Cm][NA]
   int64_t *setv;                                           // [8] set-level sums
+  int64_t *colw;                                           // [2][Xm] column totals of hpp weights
+  int64_t *PS;                                             // [6][Xm][Cm+1] rank scans per executor
+  int64_t *PA;                                             // [4][NAm][Cm+1] rank scans per accelerator
+  int64_t *UB;                                             // [NAm][Cm] users' A* max, then within-level suffix max
   int32_t *S, *dl, *ncb, *mine, *uses, *spin;              // [Cm]
   int32_t *runs;                                           // [Cm][X]
   int32_t *dca, *nra;                                      // [Cm][NA]
@@ -42,7 +51,8 @@ struct FeatTables {
 __host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
   const size_t C = Cm, CX = (size_t)Cm * Xm, CA = (size_t)Cm * NAm;
   const size_t G = Cm > 64 ? (size_t)Cm : 64;
-  const size_t n64 = 8 * C + 7 * CX + 3 * CA + 8;
+  const size_t scan = Cm > kScanC ? 6 * (size_t)Xm * (C + 1) + 4 * (size_t)NAm * (C + 1) + CA : 0;
+  const size_t n64 = 8 * C + 9 * CX + 3 * CA + 8 + 2 * (size_t)Xm + scan;
   const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G * NAm;
   const size_t n16 = C + G;
   return ((8 * n64 + 4 * n32 + 2 * n16) + 15) & ~(size_t)15;
@@ -68,10 +78,19 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.bS = d; d += CX;
   t.q = d; d += CX;
   t.qa = d; d += CX;
+  t.hpn = d; d += CX;
+  t.hpq = d; d += CX;
   t.Ahat = d; d += CA;
   t.Amax = d; d += CA;
   t.qA = d; d += CA;
   t.setv = d; d += 8;
+  t.colw = d; d += 2 * (size_t)Xm;
+  t.PS = t.PA = t.UB = nullptr;
+  if (Cm > kScanC) {
+    t.PS = d; d += 6 * (size_t)Xm * (C + 1);
+    t.PA = d; d += 4 * (size_t)NAm * (C + 1);
+    t.UB = d; d += CA;
+  }
   int32_t *i = reinterpret_cast<int32_t *>(d);
   t.S = i; i += C;
   t.dl = i; i += C;
@@ -103,8 +122,19 @@ __device__ __forceinline__ double fratio(int64_t n, int64_t m) {
 
 constexpr int64_t kQ = 65536;  // fixed-point scale of utilisation terms
 
+// hpp weight of chain h on executor e: E plus, for a busy-waiting chain, its
+// accelerator handling, else only its request overheads
+__device__ __forceinline__ int64_t hpp_w(const FeatTables &t, int h, int e, int X) {
+  const int i = h * X + e;
+  return t.Ece[i] + (t.spin[h] ? t.Acce[i] + t.epce[i] : t.epce[i]);
+}
+__device__ __forceinline__ int64_t hpp_q(const FeatTables &t, int h, int e, int X) {
+  const int i = h * X + e;
+  return t.q[i] + (t.spin[h] ? t.qa[i] : 0);
+}
+
 // Order-independent tables of a set at utilisation scale u.  Lane c owns the
-// rows of chain c; lane 0 then forms the set-level sums.  Ends synchronised.
+// rows of chain c.  Ends synchronised.
 __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables &t) {
   const int64_t c0 = b.set_chain_off[set];
   const int C = (int)(b.set_chain_off[set + 1] - c0);
@@ -194,6 +224,16 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
     t.spin[c] = b.spin[c0 + c];
   }
   __syncthreads();
+  // column totals of the hpp weights per executor
+  for (int e = threadIdx.x; e < X; e += kWave) {
+    int64_t w = 0, q = 0;
+    for (int h = 0; h < C; ++h) {
+      w += hpp_w(t, h, e, X);
+      q += hpp_q(t, h, e, X);
+    }
+    t.colw[e] = w;
+    t.colw[X + e] = q;
+  }
   if (threadIdx.x == 0) {
     int64_t sum_q = 0, sum_qA = 0, sum_dem = 0, Tmin = INT64_MAX, max_qe = 0, tot = 0;
     for (int h = 0; h < C; ++h) {
@@ -216,28 +256,47 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
     t.setv[5] = tot;
   }
   __syncthreads();
+  // OS preemption by higher process-priority executors of the same core does
+  // not depend on the chain order: per (chain, executor), the column totals
+  // over those executors minus the chain's own entries
+  for (int c = threadIdx.x; c < C; c += kWave) {
+    for (int e = 0; e < X; ++e) {
+      int64_t n = 0, q = 0;
+      for (uint32_t m = (uint32_t)t.hpx[e]; m; m &= m - 1) {
+        const int e2 = __ffs(m) - 1;
+        n += 2 * (t.colw[e2] - hpp_w(t, c, e2, X));
+        q += t.colw[X + e2] - hpp_q(t, c, e2, X);
+      }
+      t.hpn[c * X + e] = n;
+      t.hpq[c * X + e] = q;
+    }
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ void put_feat(uint16_t *row, int f, double v) {
   row[f] = bf16_rne((float)v);
 }
 
-// The 48 features of chain c under the candidate whose ranks are rk and
-// bucket levels lv, written to row[0..47].  Feature k here is feature k of
-// the documented list; each is (double)N / (double)M of exact integers.
-__device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, const int16_t *rk,
-                           const int32_t *lv, int c, uint16_t *row) {
+// Order-dependent numerators of one chain under one candidate.
+struct FeatNums {
+  int64_t n19, n20, q21, q22, n_carry, q24, n25, n_bp, n_bs, m28, n29, n_hpp, q_hpp;
+  int64_t n_acc, q33, n_bacc, n36, f37;
+  double f35;
+};
+
+// The 48 features of chain c of rank rho, written to row[0..47].  Feature k
+// here is feature k of the documented list; each is (double)N / (double)M of
+// exact integers.
+__device__ void feat_write(const DevBatch &b, int64_t set, const FeatTables &t, int c, int rho,
+                           const FeatNums &f, uint16_t *row) {
   const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
   const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
-  const int64_t a0 = b.set_accel_off[set];
-  const int NA = (int)(b.set_accel_off[set + 1] - a0);
-  const int NAm = NA > 0 ? NA : 1;
+  const int NA = (int)(b.set_accel_off[set + 1] - b.set_accel_off[set]);
   const int64_t hop = b.eps_hop[set];
-  const int rho = rk[c];
   const int64_t T = t.T[c], D = t.D[c];
   const int S = t.S[c];
   const int64_t own = t.Ec[c] + t.Acc[c] + t.epc[c] + (int64_t)(S - 1) * hop;
-  const uint32_t mine = (uint32_t)t.mine[c], uses = (uint32_t)t.uses[c];
   put_feat(row, 0, fratio(t.Ec[c], D));
   put_feat(row, 1, fratio(t.Acc[c], D));
   put_feat(row, 2, fratio(t.epc[c], D));
@@ -247,7 +306,7 @@ __device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, 
   put_feat(row, 6, fratio(S, 16));
   put_feat(row, 7, fratio(t.dl[c], 16));
   put_feat(row, 8, fratio(t.ncb[c], 32));
-  put_feat(row, 9, fratio(__popc(mine), X));
+  put_feat(row, 9, fratio(__popc((uint32_t)t.mine[c]), X));
   put_feat(row, 10, fratio(D, T));
   put_feat(row, 11, fratio(T, (int64_t)1 << 30));
   put_feat(row, 12, t.spin[c] ? 1.0 : 0.0);
@@ -257,18 +316,80 @@ __device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, 
   put_feat(row, 16, fratio(C - 1 - rho, C));
   put_feat(row, 17, rho == 0 ? 1.0 : 0.0);
   put_feat(row, 18, rho == C - 1 ? 1.0 : 0.0);
-  int n19 = 0, n20 = 0;
+  put_feat(row, 19, fratio(f.n19, C));
+  put_feat(row, 20, fratio(f.n20, C));
+  put_feat(row, 21, fratio(f.q21, kQ));
+  put_feat(row, 22, fratio(f.q22, kQ));
+  put_feat(row, 23, fratio(f.n_carry, D));
+  put_feat(row, 24, fratio(f.q24, kQ));
+  put_feat(row, 25, fratio(f.n25, C));
+  put_feat(row, 26, fratio(f.n_bp, D));
+  put_feat(row, 27, fratio(f.n_bs, D));
+  put_feat(row, 28, fratio(f.m28, D));
+  put_feat(row, 29, fratio(f.n29, C));
+  put_feat(row, 30, fratio(f.n_hpp, D));
+  put_feat(row, 31, fratio(f.q_hpp, kQ));
+  put_feat(row, 32, fratio(f.n_acc, D));
+  put_feat(row, 33, fratio(f.q33, kQ));
+  put_feat(row, 34, fratio(f.n_bacc, D));
+  put_feat(row, 35, f.f35);
+  put_feat(row, 36, fratio(f.n36, C));
+  put_feat(row, 37, f.f37 ? 1.0 : 0.0);
+  put_feat(row, 38, fratio(t.setv[0], (int64_t)X * kQ));
+  put_feat(row, 39, fratio(t.setv[4], kQ));
+  put_feat(row, 40, fratio(t.setv[1], kQ));
+  put_feat(row, 41, fratio(C, 256));
+  put_feat(row, 42, fratio(X, 8));
+  put_feat(row, 43, fratio(NA, 8));
+  put_feat(row, 44, fratio(t.setv[3], T));
+  const int64_t n_est = own + f.n_carry + f.n_bs + f.n_hpp + f.n_acc + f.n_bacc;
+  const int64_t q_est = f.q21 + f.q22 + f.q_hpp + f.q33;
+  put_feat(row, 45, fratio(n_est, D));
+  put_feat(row, 46, fratio(n_est, D) + fratio(q_est, kQ));
+  put_feat(row, 47, fratio(t.Ec[c] + t.Acc[c], t.setv[2]));
+}
+
+// Chains ranked above / below c that beat / trail it in period (RM inversions).
+__device__ __forceinline__ void rm_inversions(const FeatTables &t, const int16_t *rk, int C, int c,
+                                              int rho, FeatNums &f) {
+  const int64_t T = t.T[c];
+  int64_t n19 = 0, n20 = 0;
   for (int h = 0; h < C; ++h) {
     const int64_t Th = t.T[h];
     const int rh = rk[h];
     n19 += (rh < rho && Th > T) ? 1 : 0;
     n20 += (rh > rho && Th < T) ? 1 : 0;
   }
-  put_feat(row, 19, fratio(n19, C));
-  put_feat(row, 20, fratio(n20, C));
-  // hp on the chain's executors, blocking, hpp
-  int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0, n_hpp = 0, q_hpp = 0;
-  int n25 = 0, n29 = 0;
+  f.n19 = n19;
+  f.n20 = n20;
+}
+
+__device__ __forceinline__ void hpp_terms(const FeatTables &t, int c, int X, FeatNums &f) {
+  int64_t n = 0, q = 0;
+  for (int e = 0; e < X; ++e) {
+    const int64_t rce = t.runs[c * X + e];
+    n += rce * t.hpn[c * X + e];
+    q += rce > 0 ? t.hpq[c * X + e] : 0;
+  }
+  f.n_hpp = n;
+  f.q_hpp = q;
+}
+
+// Direct schedule: chain c under the candidate with ranks rk and bucket
+// levels lv, summing over the other chains.
+__device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, const int16_t *rk,
+                           const int32_t *lv, int c, uint16_t *row) {
+  const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
+  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
+  const int64_t a0 = b.set_accel_off[set];
+  const int NA = (int)(b.set_accel_off[set + 1] - a0);
+  const int NAm = NA > 0 ? NA : 1;
+  const int rho = rk[c];
+  const uint32_t uses = (uint32_t)t.uses[c];
+  FeatNums f;
+  rm_inversions(t, rk, C, c, rho, f);
+  int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0;
+  int64_t n25 = 0, n29 = 0;
   for (int e = 0; e < X; ++e) {
     const int64_t rce = t.runs[c * X + e];
     int64_t sq = 0, sqa = 0, scar = 0, mbl = 0, mbs = 0;
@@ -298,32 +419,11 @@ __device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, 
       n29 += nlp;
       m28 = mbs > m28 ? mbs : m28;
     }
-    for (uint32_t m = (uint32_t)t.hpx[e]; m; m &= m - 1) {
-      const int e2 = __ffs(m) - 1;
-      for (int h = 0; h < C; ++h) {
-        if (h == c) continue;
-        const int ih = h * X + e2;
-        const bool sp = t.spin[h] != 0;
-        const int64_t w = t.Ece[ih] + (sp ? t.Acce[ih] + t.epce[ih] : t.epce[ih]);
-        n_hpp += rce * 2 * w;
-        if (rce > 0) q_hpp += t.q[ih] + (sp ? t.qa[ih] : 0);
-      }
-    }
   }
-  put_feat(row, 21, fratio(q21, kQ));
-  put_feat(row, 22, fratio(q22, kQ));
-  put_feat(row, 23, fratio(n_carry, D));
-  put_feat(row, 24, fratio(q24, kQ));
-  put_feat(row, 25, fratio(n25, C));
-  put_feat(row, 26, fratio(n_bp, D));
-  put_feat(row, 27, fratio(n_bs, D));
-  put_feat(row, 28, fratio(m28, D));
-  put_feat(row, 29, fratio(n29, C));
-  put_feat(row, 30, fratio(n_hpp, D));
-  put_feat(row, 31, fratio(q_hpp, kQ));
-  // accelerators
-  int64_t n_acc = 0, q33 = 0, n_bacc = 0;
-  int n36 = 0, f37 = 0;
+  f.q21 = q21; f.q22 = q22; f.q24 = q24; f.n_carry = n_carry; f.n_bp = n_bp; f.n_bs = n_bs;
+  f.m28 = m28; f.n25 = n25; f.n29 = n29;
+  hpp_terms(t, c, X, f);
+  int64_t n_acc = 0, q33 = 0, n_bacc = 0, n36 = 0, f37 = 0;
   double f35 = 0.0;
   for (int a = 0; a < NA; ++a) {
     if (!((uses >> a) & 1u)) continue;
@@ -346,24 +446,175 @@ __device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, 
     const double lvr = fratio(lev, b.buckets[a0 + a]);
     f35 = lvr > f35 ? lvr : f35;
   }
-  put_feat(row, 32, fratio(n_acc, D));
-  put_feat(row, 33, fratio(q33, kQ));
-  put_feat(row, 34, fratio(n_bacc, D));
-  put_feat(row, 35, f35);
-  put_feat(row, 36, fratio(n36, C));
-  put_feat(row, 37, f37 ? 1.0 : 0.0);
-  put_feat(row, 38, fratio(t.setv[0], (int64_t)X * kQ));
-  put_feat(row, 39, fratio(t.setv[4], kQ));
-  put_feat(row, 40, fratio(t.setv[1], kQ));
-  put_feat(row, 41, fratio(C, 256));
-  put_feat(row, 42, fratio(X, 8));
-  put_feat(row, 43, fratio(NA, 8));
-  put_feat(row, 44, fratio(t.setv[3], T));
-  const int64_t n_est = own + n_carry + n_bs + n_hpp + n_acc + n_bacc;
-  const int64_t q_est = q21 + q22 + q_hpp + q33;
-  put_feat(row, 45, fratio(n_est, D));
-  put_feat(row, 46, fratio(n_est, D) + fratio(q_est, kQ));
-  put_feat(row, 47, fratio(t.Ec[c] + t.Acc[c], t.setv[2]));
+  f.n_acc = n_acc; f.q33 = q33; f.n_bacc = n_bacc; f.n36 = n36; f.f37 = f37; f.f35 = f35;
+  feat_write(b, set, t, c, rho, f, row);
+}
+
+// ---- prefix-scan schedule (sets of more than kScanC chains)
+
+// out[0] = 0, out[r + 1] = sum of val(r') over ranks r' <= r
+template <class F>
+__device__ __forceinline__ void scan_prefix(int C, F val, int64_t *out) {
+  const int lane = threadIdx.x;
+  int64_t carry = 0;
+  for (int rb = 0; rb < C; rb += kWave) {
+    const int r = rb + lane;
+    int64_t v = r < C ? val(r) : 0;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t n = __shfl_up(v, o);
+      if (lane >= o) v += n;
+    }
+    v += carry;
+    if (r < C) out[r + 1] = v;
+    carry = __shfl(v, kWave - 1);
+  }
+  if (lane == 0) out[0] = 0;
+}
+
+// out[r] = max of val(r') over ranks r' >= r (values >= 0), out[C] = 0
+template <class F>
+__device__ __forceinline__ void scan_suffix_max(int C, F val, int64_t *out) {
+  const int lane = threadIdx.x;
+  int64_t carry = 0;
+  for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
+    const int r = rb + lane;
+    int64_t v = r < C ? val(r) : 0;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t n = __shfl_down(v, o);
+      if (lane + o < kWave) v = n > v ? n : v;
+    }
+    v = carry > v ? carry : v;
+    if (r < C) out[r] = v;
+    carry = __shfl(v, 0);
+  }
+  if (lane == 0) out[C] = 0;
+}
+
+// Scans of one candidate (order in t.order: chain at each rank).  Per
+// executor: prefix sums of q, qa, E + A* + eps and "has a sub-chain" (HP
+// side), suffix maxima of the blocking candidates (LP side).  Per
+// accelerator: prefix sums of A-hat, its utilisation, users and positive
+// requests; then the users' largest A* in user order, turned into a suffix
+// maximum within each bucket level.  Ends synchronised.
+__device__ void feat_scans(const DevBatch &b, int64_t set, FeatTables &t) {
+  const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
+  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
+  const int64_t a0 = b.set_accel_off[set];
+  const int NA = (int)(b.set_accel_off[set + 1] - a0);
+  const int NAm = NA > 0 ? NA : 1;
+  const size_t Cp = (size_t)C + 1;
+  const int32_t *ord = t.order;
+  for (int e = 0; e < X; ++e) {
+    int64_t *P = t.PS + (size_t)e * Cp;
+    const size_t stride = (size_t)X * Cp;
+    scan_prefix(C, [&](int r) { return t.q[ord[r] * X + e]; }, P);
+    scan_prefix(C, [&](int r) { return t.qa[ord[r] * X + e]; }, P + stride);
+    scan_prefix(C, [&](int r) {
+      const int i = ord[r] * X + e;
+      return t.Ece[i] + t.Acce[i] + t.epce[i];
+    }, P + 2 * stride);
+    scan_prefix(C, [&](int r) { return (int64_t)(t.runs[ord[r] * X + e] > 0); }, P + 3 * stride);
+    scan_suffix_max(C, [&](int r) { return t.bl[ord[r] * X + e]; }, P + 4 * stride);
+    scan_suffix_max(C, [&](int r) { return t.bS[ord[r] * X + e]; }, P + 5 * stride);
+  }
+  for (int a = 0; a < NA; ++a) {
+    int64_t *P = t.PA + (size_t)a * Cp;
+    const size_t stride = (size_t)NAm * Cp;
+    scan_prefix(C, [&](int r) { return t.Ahat[ord[r] * NAm + a]; }, P);
+    scan_prefix(C, [&](int r) { return t.qA[ord[r] * NAm + a]; }, P + stride);
+    scan_prefix(C, [&](int r) { return (int64_t)(t.dca[ord[r] * NAm + a] > 0); }, P + 2 * stride);
+    scan_prefix(C, [&](int r) { return (int64_t)(t.Ahat[ord[r] * NAm + a] > 0); }, P + 3 * stride);
+  }
+  __syncthreads();
+  for (int a = 0; a < NA; ++a) {
+    const int64_t *PU = t.PA + (size_t)(2 * NAm + a) * Cp;  // users ranked above each rank
+    int64_t *U = t.UB + (size_t)a * C;
+    for (int r = threadIdx.x; r < C; r += kWave) {
+      const int h = ord[r];
+      if (t.dca[h * NAm + a] > 0) U[PU[r]] = t.Amax[h * NAm + a];
+    }
+    __syncthreads();
+    // suffix maximum within each bucket level (level of user u: u * n / m)
+    const int64_t m = PU[C];
+    const int64_t nb = b.buckets[a0 + a];
+    int64_t carry = 0, carry_lev = -1;
+    for (int64_t ub = m > 0 ? ((m - 1) / kWave) * kWave : -1; ub >= 0; ub -= kWave) {
+      const int64_t uu = ub + threadIdx.x;
+      const int64_t lev = uu < m ? (uu * nb) / m : -2;
+      int64_t v = uu < m ? U[uu] : 0;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t nv = __shfl_down(v, o);
+        const int64_t nl = __shfl_down(lev, o);
+        if ((int)threadIdx.x + o < kWave && nl == lev) v = nv > v ? nv : v;
+      }
+      if (lev == carry_lev) v = carry > v ? carry : v;
+      if (uu < m) U[uu] = v;
+      carry = __shfl(v, 0);
+      carry_lev = __shfl(lev, 0);
+    }
+    __syncthreads();
+  }
+}
+
+// Prefix-scan schedule: chain c under the candidate whose scans feat_scans wrote.
+__device__ void feat_chain_scan(const DevBatch &b, int64_t set, const FeatTables &t, int c,
+                                uint16_t *row) {
+  const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
+  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
+  const int64_t a0 = b.set_accel_off[set];
+  const int NA = (int)(b.set_accel_off[set + 1] - a0);
+  const int NAm = NA > 0 ? NA : 1;
+  const size_t Cp = (size_t)C + 1;
+  const int rho = t.rank[c];
+  const uint32_t uses = (uint32_t)t.uses[c];
+  FeatNums f;
+  rm_inversions(t, t.rank, C, c, rho, f);
+  int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0;
+  int64_t n25 = 0, n29 = 0;
+  const size_t stride = (size_t)X * Cp;
+  for (int e = 0; e < X; ++e) {
+    const int64_t rce = t.runs[c * X + e];
+    const int64_t *P = t.PS + (size_t)e * Cp;
+    const int64_t sq = P[rho], sqa = P[stride + rho], scar = P[2 * stride + rho];
+    const int64_t nhp = P[3 * stride + rho];
+    const int64_t nlp = P[3 * stride + C] - P[3 * stride + rho + 1];
+    const int64_t mbl = P[4 * stride + rho + 1], mbs = P[5 * stride + rho + 1];
+    n_carry += rce * 2 * scar;
+    n_bp += rce * mbl;
+    n_bs += rce * mbs;
+    if (rce > 0) {
+      q21 += sq;
+      q22 += sqa;
+      q24 = sq + sqa > q24 ? sq + sqa : q24;
+      n25 += nhp;
+      n29 += nlp;
+      m28 = mbs > m28 ? mbs : m28;
+    }
+  }
+  f.q21 = q21; f.q22 = q22; f.q24 = q24; f.n_carry = n_carry; f.n_bp = n_bp; f.n_bs = n_bs;
+  f.m28 = m28; f.n25 = n25; f.n29 = n29;
+  hpp_terms(t, c, X, f);
+  int64_t n_acc = 0, q33 = 0, n_bacc = 0, n36 = 0, f37 = 0;
+  double f35 = 0.0;
+  const size_t astride = (size_t)NAm * Cp;
+  for (int a = 0; a < NA; ++a) {
+    if (!((uses >> a) & 1u)) continue;
+    const int64_t *P = t.PA + (size_t)a * Cp;
+    const int64_t u = P[2 * astride + rho];  // users ranked above c
+    const int64_t m = P[2 * astride + C];
+    const int64_t nb = b.buckets[a0 + a];
+    const int64_t lev = (u * nb) / m;
+    n_acc += 2 * (int64_t)t.nra[c * NAm + a] * P[rho];
+    q33 += P[astride + rho];
+    n36 += u;
+    f37 |= P[3 * astride + rho] > 0;
+    const int64_t bacc = (u + 1 < m && ((u + 1) * nb) / m == lev) ? t.UB[(size_t)a * C + u + 1] : 0;
+    n_bacc += (int64_t)t.dca[c * NAm + a] * bacc;
+    const double lvr = fratio(lev, nb);
+    f35 = lvr > f35 ? lvr : f35;
+  }
+  f.n_acc = n_acc; f.q33 = q33; f.n_bacc = n_bacc; f.n36 = n36; f.f37 = f37; f.f35 = f35;
+  feat_write(b, set, t, c, rho, f, row);
 }
 
 // Work item i: explicit pairs (one candidate each), or in range mode a run of
@@ -417,9 +668,22 @@ __global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
       t.rank[c] = (int16_t)r;
     }
     __syncthreads();
-    int G = C <= 64 ? 64 / C : 1;
-    G = G < kMaxGroup ? G : kMaxGroup;
     int64_t cur = 0;
+    if (C > kScanC) {
+      for (int64_t k = k0; k < k0 + n_k; ++k) {
+        walk_order(t.order, t.rank, C, L.seed, set, cur, k, t.buf);
+        cur = k;
+        feat_scans(L.b, set, t);
+        const int64_t o = out0 + (k - k0);
+        for (int c = lane; c < C; c += kWave)
+          feat_chain_scan(L.b, set, t, c, L.feat + ((size_t)o * L.row_stride + c) * 48);
+        if (lane == 0) L.count[o] = C;
+        __syncthreads();
+      }
+      continue;
+    }
+    int G = 64 / C;
+    G = G < kMaxGroup ? G : kMaxGroup;
     for (int64_t kb = k0; kb < k0 + n_k; kb += G) {
       const int ng = (int)(k0 + n_k - kb < G ? k0 + n_k - kb : G);
       // ranks of the group's candidates

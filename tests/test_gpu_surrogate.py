@@ -60,6 +60,13 @@ def test_features_bit_exact(preset, n_sets, n_pairs, utils):
 def test_features_large_sets_and_edges():
     cs = chaingen.generate("large", 2)
     _check_features(cs, np.array([[0, 0, 1000], [1, 1023, 400]], np.int64))
+    # 65-140 chains (the prefix-scan schedule over more than one 64-rank
+    # chunk), three accelerators with five bucket levels each
+    mid = chaingen.PRESETS["large"].replace(
+        chains=(65, 140), n_accel=3, max_seg_per_cb=2, n_buckets=5, eps=391_000,
+        kappa=129_180, eps_hop=391_000, n_exec=5)
+    cs = chaingen.generate(mid, 3)
+    _check_features(cs, _pairs(cs, 6, 8, utils=(1000, 300)))
     # a lone chain, a set with no accelerator segments, a 1-chain walk
     lone = chaingen.from_sets([
         {"chains": [{"T": 100, "D": 90, "prio": 1, "cbs": [{"E": 7, "exec": 0, "segs": [(3, 0)]}]}],
