@@ -41,11 +41,12 @@ def log(msg):
 
 
 # HBM bytes per full-mode launch of the analysis kernel on the default
-# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled
-# by the counters' reading for the 1 GiB calibration copy.  Valid only for the
-# kernel source with this SHA-256; reported as null for any other.
-TRAFFIC = {"sha256": "5139d23105e9a3d138665b1160059149b61d82c6cf0b91a0c6c4caf0342b9172",
-           "bytes_per_launch": 41.76e9, "sets": 1_000_000, "waves_per_cu": 12}
+# workload (mean over the launches of a sweep, one per size class and level),
+# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
+# counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
+# source with this SHA-256 at the same waves per CU; null otherwise.
+TRAFFIC = {"sha256": "555ffae40d89660878ae1fc7b9fbf347e90c652194707ab0c9a62c9e3ed8e5eb",
+           "bytes_per_launch": 15.17e9, "sets": 1_000_000, "waves_per_cu": 16}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
@@ -196,6 +197,126 @@ def search_section(args, torch, log):
                 entry["guided_with_fallback"]["mean_exact_evals"], top_k,
                 entry["guided_top_k_only"]["sets_per_s"], entry["guided_top_k_only"]["found_frac"]))
     res["setup_s"] = time.perf_counter() - t0
+    return res, net
+
+
+def large_section(args, torch, log, net):
+    """Sets of 256 chains x 2-32 callbacks, 8 executors, one accelerator, U ~
+    U(0.3, 0.95), half the callbacks with a segment: the exact analysis of the
+    uploaded rate-monotonic order, network scores of 1,024 candidate orders
+    per set, and the exact confirmation of the top 32, captured together in one
+    HIP graph; plain search over the same 1,024 candidates on a subset for
+    comparison.  Times are HIP events on the launch stream."""
+    from paper_2404_06452_amd import _paam, chaingen
+
+    n_cand, top_k, seed = 1024, 32, 2404
+    stream = torch.cuda.Stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    t0 = time.perf_counter()
+    cs = chaingen.generate("large", args.large_sets)
+    dev = _paam.Chainset(cs, device="cuda:0")
+    n = cs.n_sets
+    m = min(args.large_plain_sets, n)
+    sub = _paam.Chainset(cs.subset(range(m)), device="cuda:0")
+    log("large sets: %d sets (%d chains, %d callbacks, %d segments) ready in %.1f s" % (
+        n, cs.n_chains, cs.n_callbacks, cs.n_segments, time.perf_counter() - t0))
+    res = {"workload": "%d chain sets of 256 chains x 2-32 callbacks, 8 executors, 1 accelerator, "
+                       "U ~ U(0.3, 0.95), 50 %% of callbacks with a segment; %d candidate orders "
+                       "per set, top %d confirmed exactly; plain search on the first %d sets" % (
+                           n, n_cand, top_k, m),
+           "sets": n, "chains": cs.n_chains, "callbacks": cs.n_callbacks,
+           "segments": cs.n_segments}
+    wout = _paam.WcrtOut(dev, False)
+    sout = _paam.SearchOut(dev)
+    pout = _paam.SearchOut(sub)
+    scores = torch.empty(n * n_cand, dtype=torch.float32, device="cuda:0")
+    levels = [("workload_utilisation", 1000)]
+    if args.large_util:
+        levels.append(("scaled_%g_permille" % args.large_util, args.large_util))
+    for name, util in levels:
+        wo = _paam.wcrt_opts(full=False, util_permille=util)
+        so = _paam.search_opts(n_cand, seed, util_permille=util)
+        go = _paam.search_opts(n_cand, seed, guided=True, top_k=top_k, fallback=False,
+                               scores=scores, util_permille=util)
+        po = _paam.search_opts(n_cand, seed, util_permille=util)
+        wws = _paam.workspace(_paam.paam_wcrt_bytes(dev, wo))
+        sws = _paam.workspace(_paam.paam_score_bytes(dev, so))
+        gws = _paam.workspace(_paam.paam_search_bytes(dev, go))
+        pws = _paam.workspace(_paam.paam_search_bytes(sub, po))
+
+        def analyse(s):
+            _paam.paam_wcrt_batch(dev, wo, wout, wws, s)
+
+        def score(s):
+            _paam.paam_score_candidates(dev, so, net.params, net.packed, scores, sws, s)
+
+        def confirm(s):
+            _paam.paam_priority_search(dev, go, sout, gws, s)
+
+        t_an = timed(lambda: analyse(stream))
+        t_sc = timed(lambda: score(stream))
+        t_gd = timed(lambda: confirm(stream))
+        ref = (wout.set_sched.clone(), sout.found.clone(), sout.n_exact.clone())
+        # the three steps as one captured graph, replayed; every replay must
+        # reproduce the eager outputs
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            s = torch.cuda.current_stream()
+            analyse(s)
+            score(s)
+            confirm(s)
+        torch.cuda.synchronize()
+        t_graph = []
+        for _ in range(2):
+            t_graph.append(timed(graph.replay))
+            assert torch.equal(ref[0], wout.set_sched) and torch.equal(ref[1], sout.found) and \
+                torch.equal(ref[2], sout.n_exact), "graph replay differs"
+        del graph
+        t_pl = timed(lambda: _paam.paam_priority_search(sub, po, pout, pws, stream))
+        rm = ref[0].cpu().numpy()
+        found_g = ref[1].cpu().numpy()
+        evals_g = ref[2].cpu().numpy()
+        found_p = pout.found.cpu().numpy()
+        evals_p = pout.n_exact.cpu().numpy()
+        fp = int((found_p >= 0).sum())
+        entry = {
+            "util_scale": util / 1000,
+            "rm_analysis": {"sets_per_s": n / t_an, "ms": t_an * 1e3,
+                            "schedulable_frac": float((rm == 1).mean())},
+            "scoring": {"candidates_per_s": n * n_cand / t_sc, "ms": t_sc * 1e3},
+            "guided_top_k": {"sets_per_s": n / (t_sc + t_gd), "search_ms": t_gd * 1e3,
+                             "found_frac": float((found_g >= 0).mean()),
+                             "mean_exact_evals": float(evals_g.mean()),
+                             "found_frac_first_subset": float((found_g[:m] >= 0).mean()),
+                             "found_vs_plain_on_subset": (float((found_g[:m] >= 0).sum() / fp)
+                                                          if fp else None)},
+            "graph": {"steps": "RM analysis + scoring + top-%d confirmation" % top_k,
+                      "ms": float(min(t_graph)) * 1e3, "sets_per_s": n / min(t_graph)},
+            "plain_subset": {"sets": m, "sets_per_s": m / t_pl, "ms": t_pl * 1e3,
+                             "found_frac": float((found_p >= 0).mean()),
+                             "mean_exact_evals": float(evals_p.mean())},
+        }
+        res[name] = entry
+        log("large %s: RM %.3g sets/s (sched %.3f) | score %.3g cand/s | guided top-%d %.3g sets/s "
+            "found %.3f evals %.1f | graph %.1f ms | plain (%d sets) %.3g sets/s found %.3f "
+            "evals %.1f" % (
+                name, entry["rm_analysis"]["sets_per_s"], entry["rm_analysis"]["schedulable_frac"],
+                entry["scoring"]["candidates_per_s"], top_k, entry["guided_top_k"]["sets_per_s"],
+                entry["guided_top_k"]["found_frac"], entry["guided_top_k"]["mean_exact_evals"],
+                entry["graph"]["ms"], m, entry["plain_subset"]["sets_per_s"],
+                entry["plain_subset"]["found_frac"], entry["plain_subset"]["mean_exact_evals"]))
+        del wws, sws, gws, pws
+    res["setup_s"] = time.perf_counter() - t0
     return res
 
 
@@ -213,6 +334,13 @@ def main():
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--train-epochs", type=int, default=2)
     ap.add_argument("--skip-search", action="store_true")
+    ap.add_argument("--large-sets", type=int, default=10000,
+                    help="sets of 256 chains for the large-set section (0 skips it)")
+    ap.add_argument("--large-plain-sets", type=int, default=500,
+                    help="sets of the large batch searched plainly for comparison")
+    ap.add_argument("--large-util", type=int, default=0,
+                    help="optional second utilisation scale of the large-set section, in "
+                         "permille (0: the workload's utilisation only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the analysis shards across GPUs by set range with no "
@@ -390,7 +518,10 @@ def main():
     if not args.skip_search:
         del graph, eager, dev, outs, ws, vout
         torch.cuda.empty_cache()
-        line["search"] = search_section(args, torch, log)
+        line["search"], net = search_section(args, torch, log)
+        torch.cuda.empty_cache()
+        if args.large_sets > 0:
+            line["large"] = large_section(args, torch, log, net)
     print(json.dumps(line), flush=True)
     if mism:
         sys.exit(1)

@@ -38,6 +38,7 @@ struct FeatTables {
   int64_t *PS;                                             // [6][Xm][Cm+1] rank scans per executor
   int64_t *PA;                                             // [4][NAm][Cm+1] rank scans per accelerator
   int64_t *UB;                                             // [NAm][Cm] users' A* max, then within-level suffix max
+  int32_t *inv;                                            // [2][Cm] RM inversions above / below
   int32_t *S, *dl, *ncb, *mine, *uses, *spin;              // [Cm]
   int32_t *runs;                                           // [Cm][X]
   int32_t *dca, *nra;                                      // [Cm][NA]
@@ -53,7 +54,7 @@ __host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
   const size_t G = Cm > 64 ? (size_t)Cm : 64;
   const size_t scan = Cm > kScanC ? 6 * (size_t)Xm * (C + 1) + 4 * (size_t)NAm * (C + 1) + CA : 0;
   const size_t n64 = 8 * C + 9 * CX + 3 * CA + 8 + 2 * (size_t)Xm + scan;
-  const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G * NAm;
+  const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G * NAm + (Cm > kScanC ? 2 * C : 0);
   const size_t n16 = C + G;
   return ((8 * n64 + 4 * n32 + 2 * n16) + 15) & ~(size_t)15;
 }
@@ -105,6 +106,11 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.order = i; i += C;
   t.buf = i; i += 64;
   t.levelg = i; i += G * NAm;
+  t.inv = nullptr;
+  if (Cm > kScanC) {
+    t.inv = i;
+    i += 2 * C;
+  }
   int16_t *h = reinterpret_cast<int16_t *>(i);
   t.rank = h; h += C;
   t.rankg = h;
@@ -452,42 +458,77 @@ __device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, 
 
 // ---- prefix-scan schedule (sets of more than kScanC chains)
 
-// out[0] = 0, out[r + 1] = sum of val(r') over ranks r' <= r
-template <class F>
-__device__ __forceinline__ void scan_prefix(int C, F val, int64_t *out) {
-  const int lane = threadIdx.x;
-  int64_t carry = 0;
-  for (int rb = 0; rb < C; rb += kWave) {
-    const int r = rb + lane;
-    int64_t v = r < C ? val(r) : 0;
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int64_t n = __shfl_up(v, o);
-      if (lane >= o) v += n;
-    }
-    v += carry;
-    if (r < C) out[r + 1] = v;
-    carry = __shfl(v, kWave - 1);
+// Wave-wide inclusive prefix sum and suffix maximum over 64 lanes.
+__device__ __forceinline__ int64_t wave_incl_sum(int64_t v) {
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t n = __shfl_up(v, o);
+    if ((int)threadIdx.x >= o) v += n;
   }
-  if (lane == 0) out[0] = 0;
+  return v;
+}
+__device__ __forceinline__ int64_t wave_incl_suffix_max(int64_t v) {
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t n = __shfl_down(v, o);
+    if ((int)threadIdx.x + o < kWave) v = n > v ? n : v;
+  }
+  return v;
 }
 
-// out[r] = max of val(r') over ranks r' >= r (values >= 0), out[C] = 0
-template <class F>
-__device__ __forceinline__ void scan_suffix_max(int C, F val, int64_t *out) {
+// K prefix sums at once: out[k][0] = 0 and out[k][r + 1] = sum of the k-th
+// value of ranks r' <= r (arrays of C + 1 at out + k * stride).  load(r, v)
+// fills v[0..K-1] for a rank below C; each 64-rank chunk issues all its loads
+// before any store.
+template <int K, class F>
+__device__ __forceinline__ void scan_prefix_k(int C, F load, int64_t *out, size_t stride) {
   const int lane = threadIdx.x;
-  int64_t carry = 0;
+  int64_t carry[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) carry[k] = 0;
+  for (int rb = 0; rb < C; rb += kWave) {
+    const int r = rb + lane;
+    int64_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0;
+    if (r < C) load(r, v);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t x = wave_incl_sum(v[k]) + carry[k];
+      if (r < C) out[k * stride + r + 1] = x;
+      carry[k] = __shfl(x, kWave - 1);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k * stride] = 0;
+  }
+}
+
+// K suffix maxima (values >= 0): out[k][r] = max of the k-th value of ranks
+// r' >= r, out[k][C] = 0.
+template <int K, class F>
+__device__ __forceinline__ void scan_suffix_max_k(int C, F load, int64_t *out, size_t stride) {
+  const int lane = threadIdx.x;
+  int64_t carry[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) carry[k] = 0;
   for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
     const int r = rb + lane;
-    int64_t v = r < C ? val(r) : 0;
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int64_t n = __shfl_down(v, o);
-      if (lane + o < kWave) v = n > v ? n : v;
+    int64_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0;
+    if (r < C) load(r, v);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      int64_t x = wave_incl_suffix_max(v[k]);
+      x = carry[k] > x ? carry[k] : x;
+      if (r < C) out[k * stride + r] = x;
+      carry[k] = __shfl(x, 0);
     }
-    v = carry > v ? carry : v;
-    if (r < C) out[r] = v;
-    carry = __shfl(v, 0);
   }
-  if (lane == 0) out[C] = 0;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k * stride + C] = 0;
+  }
 }
 
 // Scans of one candidate (order in t.order: chain at each rank).  Per
@@ -504,26 +545,31 @@ __device__ void feat_scans(const DevBatch &b, int64_t set, FeatTables &t) {
   const int NAm = NA > 0 ? NA : 1;
   const size_t Cp = (size_t)C + 1;
   const int32_t *ord = t.order;
+  const size_t stride = (size_t)X * Cp;
   for (int e = 0; e < X; ++e) {
     int64_t *P = t.PS + (size_t)e * Cp;
-    const size_t stride = (size_t)X * Cp;
-    scan_prefix(C, [&](int r) { return t.q[ord[r] * X + e]; }, P);
-    scan_prefix(C, [&](int r) { return t.qa[ord[r] * X + e]; }, P + stride);
-    scan_prefix(C, [&](int r) {
+    scan_prefix_k<4>(C, [&](int r, int64_t *v) {
       const int i = ord[r] * X + e;
-      return t.Ece[i] + t.Acce[i] + t.epce[i];
-    }, P + 2 * stride);
-    scan_prefix(C, [&](int r) { return (int64_t)(t.runs[ord[r] * X + e] > 0); }, P + 3 * stride);
-    scan_suffix_max(C, [&](int r) { return t.bl[ord[r] * X + e]; }, P + 4 * stride);
-    scan_suffix_max(C, [&](int r) { return t.bS[ord[r] * X + e]; }, P + 5 * stride);
+      v[0] = t.q[i];
+      v[1] = t.qa[i];
+      v[2] = t.Ece[i] + t.Acce[i] + t.epce[i];
+      v[3] = t.runs[i] > 0;
+    }, P, stride);
+    scan_suffix_max_k<2>(C, [&](int r, int64_t *v) {
+      const int i = ord[r] * X + e;
+      v[0] = t.bl[i];
+      v[1] = t.bS[i];
+    }, P + 4 * stride, stride);
   }
+  const size_t astride = (size_t)NAm * Cp;
   for (int a = 0; a < NA; ++a) {
-    int64_t *P = t.PA + (size_t)a * Cp;
-    const size_t stride = (size_t)NAm * Cp;
-    scan_prefix(C, [&](int r) { return t.Ahat[ord[r] * NAm + a]; }, P);
-    scan_prefix(C, [&](int r) { return t.qA[ord[r] * NAm + a]; }, P + stride);
-    scan_prefix(C, [&](int r) { return (int64_t)(t.dca[ord[r] * NAm + a] > 0); }, P + 2 * stride);
-    scan_prefix(C, [&](int r) { return (int64_t)(t.Ahat[ord[r] * NAm + a] > 0); }, P + 3 * stride);
+    scan_prefix_k<4>(C, [&](int r, int64_t *v) {
+      const int i = ord[r] * NAm + a;
+      v[0] = t.Ahat[i];
+      v[1] = t.qA[i];
+      v[2] = t.dca[i] > 0;
+      v[3] = t.Ahat[i] > 0;
+    }, t.PA + (size_t)a * Cp, astride);
   }
   __syncthreads();
   for (int a = 0; a < NA; ++a) {
@@ -556,6 +602,59 @@ __device__ void feat_scans(const DevBatch &b, int64_t set, FeatTables &t) {
   }
 }
 
+// RM inversion counts of every chain (t.inv) under the order in t.rank:
+// computed in full, or, when the order differs from the previous one by the
+// single swap of positions pa and pb, updated.  A chain ranked strictly
+// between the two positions trades the swapped chain above it for the other;
+// chains outside keep both on the same side; the two swapped chains are
+// counted again by the whole wave.  Ends synchronised.
+__device__ void feat_inversions(const FeatTables &t, int C, int pa, int pb, bool incremental) {
+  const int lane = threadIdx.x;
+  if (!incremental) {
+    for (int c = lane; c < C; c += kWave) {
+      FeatNums f;
+      rm_inversions(t, t.rank, C, c, t.rank[c], f);
+      t.inv[c] = (int32_t)f.n19;
+      t.inv[C + c] = (int32_t)f.n20;
+    }
+    __syncthreads();
+    return;
+  }
+  const int lo = pa < pb ? pa : pb, hi = pa < pb ? pb : pa;
+  const int up = t.order[lo], down = t.order[hi];  // moved up to lo / down to hi
+  const int64_t Tu = t.T[up], Td = t.T[down];
+  for (int c = lane; c < C; c += kWave) {
+    const int r = t.rank[c];
+    if (r > lo && r < hi) {
+      const int64_t Tc = t.T[c];
+      t.inv[c] += (Tu > Tc ? 1 : 0) - (Td > Tc ? 1 : 0);
+      t.inv[C + c] += (Td < Tc ? 1 : 0) - (Tu < Tc ? 1 : 0);
+    }
+  }
+  int32_t a19 = 0, a20 = 0, b19 = 0, b20 = 0;
+  for (int h = lane; h < C; h += kWave) {
+    const int rh = t.rank[h];
+    const int64_t Th = t.T[h];
+    a19 += (rh < lo && Th > Tu) ? 1 : 0;
+    a20 += (rh > lo && Th < Tu) ? 1 : 0;
+    b19 += (rh < hi && Th > Td) ? 1 : 0;
+    b20 += (rh > hi && Th < Td) ? 1 : 0;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    a19 += __shfl_xor(a19, o);
+    a20 += __shfl_xor(a20, o);
+    b19 += __shfl_xor(b19, o);
+    b20 += __shfl_xor(b20, o);
+  }
+  if (lane == 0) {
+    t.inv[up] = a19;
+    t.inv[C + up] = a20;
+    t.inv[down] = b19;
+    t.inv[C + down] = b20;
+  }
+  __syncthreads();
+}
+
 // Prefix-scan schedule: chain c under the candidate whose scans feat_scans wrote.
 __device__ void feat_chain_scan(const DevBatch &b, int64_t set, const FeatTables &t, int c,
                                 uint16_t *row) {
@@ -568,7 +667,8 @@ __device__ void feat_chain_scan(const DevBatch &b, int64_t set, const FeatTables
   const int rho = t.rank[c];
   const uint32_t uses = (uint32_t)t.uses[c];
   FeatNums f;
-  rm_inversions(t, t.rank, C, c, rho, f);
+  f.n19 = t.inv[c];
+  f.n20 = t.inv[C + c];
   int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0;
   int64_t n25 = 0, n29 = 0;
   const size_t stride = (size_t)X * Cp;
@@ -669,10 +769,13 @@ __global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
     }
     __syncthreads();
     int64_t cur = 0;
-    if (C > kScanC) {
+    if (!kLds && C > kScanC) {
       for (int64_t k = k0; k < k0 + n_k; ++k) {
+        const bool step = k > k0 && k == cur + 1;
         walk_order(t.order, t.rank, C, L.seed, set, cur, k, t.buf);
         cur = k;
+        const int32_t pq = step ? swap_positions(L.seed, set, k, C) : 0;
+        feat_inversions(t, C, pq & 0xffff, pq >> 16, step);
         feat_scans(L.b, set, t);
         const int64_t o = out0 + (k - k0);
         for (int c = lane; c < C; c += kWave)
@@ -682,7 +785,7 @@ __global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
       }
       continue;
     }
-    int G = 64 / C;
+    int G = C <= 64 ? 64 / C : 1;
     G = G < kMaxGroup ? G : kMaxGroup;
     for (int64_t kb = k0; kb < k0 + n_k; kb += G) {
       const int ng = (int)(k0 + n_k - kb < G ? k0 + n_k - kb : G);
@@ -1016,7 +1119,11 @@ size_t feat_wave_bytes(const DevBatch &b) {
   return (feat_table_bytes(b.max_C, b.max_X, NAm) + 255) & ~(size_t)255;
 }
 
-bool feat_in_lds(const DevBatch &b) { return feat_wave_bytes(b) <= kFeatLdsMax; }
+// Sets of more than kScanC chains take the prefix-scan schedule, which keeps
+// its tables in global memory.
+bool feat_in_lds(const DevBatch &b) {
+  return b.max_C <= kScanC && feat_wave_bytes(b) <= kFeatLdsMax;
+}
 
 int launch_features(const FeatLaunch &L, void *stream) {
   hipStream_t st = (hipStream_t)stream;

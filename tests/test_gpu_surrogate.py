@@ -62,9 +62,7 @@ def test_features_large_sets_and_edges():
     _check_features(cs, np.array([[0, 0, 1000], [1, 1023, 400]], np.int64))
     # 65-140 chains (the prefix-scan schedule over more than one 64-rank
     # chunk), three accelerators with five bucket levels each
-    mid = chaingen.PRESETS["large"].replace(
-        chains=(65, 140), n_accel=3, max_seg_per_cb=2, n_buckets=5, eps=391_000,
-        kappa=129_180, eps_hop=391_000, n_exec=5)
+    mid = chaingen.PRESETS["large"].replace(**MID)
     cs = chaingen.generate(mid, 3)
     _check_features(cs, _pairs(cs, 6, 8, utils=(1000, 300)))
     # a lone chain, a set with no accelerator segments, a 1-chain walk
@@ -214,11 +212,19 @@ def test_backward_and_adam_match_oracle():
     assert np.array_equal(pk, exp)
 
 
-def test_score_candidates_equals_explicit_path():
-    cs = chaingen.generate("search", 12)
+MID = dict(chains=(65, 140), n_accel=3, max_seg_per_cb=2, n_buckets=5, eps=391_000,
+           kappa=129_180, eps_hop=391_000, n_exec=5)
+
+
+@pytest.mark.parametrize("preset,n_sets,n_cand", [("search", 12, 70), ("mid", 3, 150)])
+def test_score_candidates_equals_explicit_path(preset, n_sets, n_cand):
+    # range mode walks each run of 64 candidates one swap at a time (updated
+    # inversion counts on sets of more than 64 chains); the explicit path
+    # computes every pair from scratch
+    params = chaingen.PRESETS["large"].replace(**MID) if preset == "mid" else preset
+    cs = chaingen.generate(params, n_sets)
     dev = _paam.Chainset(cs, device=DEV)
     net = _paam.Network(chaingen.mlp_init(5), device=DEV)
-    n_cand = 70
     sc = _paam.score(dev, net, n_cand, SEED).cpu().numpy()
     pairs = np.array([[s, k, 1000] for s in range(cs.n_sets) for k in range(n_cand)], np.int64)
     f = _paam.features(dev, pairs, SEED)
