@@ -66,14 +66,15 @@ __device__ __forceinline__ bool ratio_gt(double Ra, int64_t Da, double Rb, int64
 // LDS of one wave.  Tables by rank (0 = highest priority) with row stride C.
 struct Lds {
   double2 *KR;                       // [C] (2T-1, 1/T up) of the chain at a rank
-  double *cap, *Dd, *partial;        // [C]
+  double *Dd, *partial;              // [C] deadline, running end-to-end sum
   double *Ahat, *amax, *Bacc;        // [NA][C]
-  double *Ece, *epsce, *Hs;          // [X][C] per chain and executor: E sum, eps sum, H* sum
   double *WP, *Pt;                   // [X][C] hp+hpp weight (rank above), hpp weight (below)
-  double *SB;                        // [X][C] blocking candidates (aliases Pt before Theorem 1)
+  double *SB;                        // [X][C] blocking candidates, then staging of the first build
   int32_t *perm, *rank, *nrun, *spinf;  // [C]
   int32_t *level, *uses;             // [NA][C]
-  int32_t *wmin, *pmax;              // [X] lowest rank whose WP changed, highest whose Pt changed
+  int32_t *wmin, *pmax;              // [2][X] lowest rank whose WP changed, highest whose Pt
+                                     // changed: as seen by this sweep, as recorded for the next
+  int32_t *lpx;                      // [X] executors of the core with lower process priority
   int32_t *misc;                     // [16]
 };
 
@@ -87,18 +88,14 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   Lds l;
   double *d = reinterpret_cast<double *>(base);
   l.KR = reinterpret_cast<double2 *>(d); d += 2 * Cm;
-  l.cap = d; d += Cm;
   l.Dd = d; d += Cm;
   l.partial = d; d += Cm;
   l.Ahat = d; d += NAm * Cm;
   l.amax = d; d += NAm * Cm;
   l.Bacc = d; d += NAm * Cm;
-  l.Ece = d; d += Xm * Cm;
-  l.epsce = d; d += Xm * Cm;
-  l.Hs = d; d += Xm * Cm;
   l.WP = d; d += Xm * Cm;
   l.Pt = d; d += Xm * Cm;
-  l.SB = l.Pt;
+  l.SB = d; d += Xm * Cm;
   int32_t *i = reinterpret_cast<int32_t *>(d);
   l.perm = i; i += Cm;
   l.rank = i; i += Cm;
@@ -106,8 +103,9 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   l.spinf = i; i += Cm;
   l.level = i; i += NAm * Cm;
   l.uses = i; i += NAm * Cm;
-  l.wmin = i; i += Xm;
-  l.pmax = i; i += Xm;
+  l.wmin = i; i += 2 * Xm;
+  l.pmax = i; i += 2 * Xm;
+  l.lpx = i; i += Xm;
   l.misc = i;
   return l;
 }
@@ -159,6 +157,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   const int32_t u = o.util_permille;
   const bool full = o.full != 0;
   const double hop = (double)b.eps_hop[set];
+  const double capm = (double)o.cap_mult;  // cap of a chain = capm * D
 
   // ---- chain tables in rank order (rank 0 = highest priority) ----
   for (int c = lane; c < C; c += kWave) {
@@ -168,7 +167,6 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     L.KR[rho] = make_double2(b.Kd[c0 + c], b.rcp[c0 + c]);
     const int64_t D = b.D[c0 + c];
     L.Dd[rho] = (double)D;
-    L.cap[rho] = (double)D * (double)o.cap_mult;
     L.nrun[rho] = b.chain_nrun[c0 + c];
     L.spinf[rho] = b.spin[c0 + c];
     L.partial[rho] = 0.0;
@@ -179,11 +177,17 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     L.uses[i] = 0;
   }
   for (int i = lane; i < X * C; i += kWave) {
-    L.Ece[i] = 0.0;
-    L.epsce[i] = 0.0;
-    L.Hs[i] = 0.0;
+    L.WP[i] = 0.0;
+    L.Pt[i] = 0.0;
     L.SB[i] = 0.0;
-    L.WP[i] = -1.0;  // the first table build always registers a change
+  }
+  for (int e = lane; e < X; e += kWave) {
+    uint32_t m = 0;
+    for (int e2 = 0; e2 < X; ++e2)
+      if ((b.hpx_mask[x0 + e2] >> e) & 1u) m |= 1u << e2;
+    L.lpx[e] = (int32_t)m;
+    L.wmin[X + e] = C;
+    L.pmax[X + e] = -1;
   }
   if (lane == 0) L.misc[0] = 0;  // iteration guard tripped
   __syncthreads();
@@ -249,7 +253,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       a = b.seg_accel[g0 + g];
       rho = L.rank[b.seg_chain[g0 + g]];
       base = S.segAs[g] + L.Bacc[a * C + rho];
-      capv = L.cap[rho];
+      capv = L.Dd[rho] * capm;
     }
     const double *Ah = L.Ahat + a * C;
     double h = 0.0;
@@ -315,8 +319,6 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       bmax = fmax(bmax, bj);
     }
     lds_max(&L.SB[e * C + rho], bmax);
-    atomicAdd(&L.Ece[e * C + rho], E);
-    atomicAdd(&L.epsce[e * C + rho], eps);
     const bool needL3 =
         delta > 0 && (o.bound == PAAM_BOUND_L3 || (o.bound == PAAM_BOUND_MIN && delta >= 2));
     // H* of a sub-chain that does not need Lemma 3 during the iteration.  With
@@ -328,7 +330,10 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       if (((accm >> a) & 1) && L.misc[1 + a] < rho) hp_acc = true;
     double hs0 = delta == 0 ? 0.0 : (hp_acc || o.bound == PAAM_BOUND_L2 ? L2 : A0) + eps;
     if (needL3) hs0 = 0.0;  // a valid start below the fixed point
-    atomicAdd(&L.Hs[e * C + rho], hs0);
+    // per chain and executor: E + H* (own executor's weight) in WP, and
+    // E + spin() (H* if the chain busy-waits, else its epsilon sum) in Pt
+    atomicAdd(&L.WP[e * C + rho], E + hs0);
+    atomicAdd(&L.Pt[e * C + rho], E + (L.spinf[rho] ? hs0 : eps));
     S.r[s] = 0.0;
     S.hs[s] = hs0;
     S.cst[s] = E;  // blocking added below
@@ -355,7 +360,23 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     S.cst[s] += rho + 1 < C ? L.SB[e * C + rho + 1] : 0.0;
   }
   __syncthreads();
-  for (int i = lane; i < X * C; i += kWave) L.Pt[i] = -1.0;  // SB is dead from here on
+  // interference weights at the starting H*: WP[e][h] = E + H* of h on e (hp
+  // term of a lower-ranked chain) + hpp weight; Pt[e][h] = hpp weight alone,
+  // the sum over the core's higher-priority executors e2 of E + spin() of h
+  // on e2.  From here on every change of an H* is added to the weights it
+  // enters, and the ranks it touches are recorded for the next sweep.
+  for (int i = lane; i < X * C; i += kWave) {
+    const int e = i / C, h = i - e * C;
+    double p = 0.0;
+    for (uint32_t m = b.hpx_mask[x0 + e]; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
+    L.SB[i] = p;  // blocking candidates are dead
+  }
+  __syncthreads();
+  for (int i = lane; i < X * C; i += kWave) {
+    L.WP[i] += L.SB[i];
+    L.Pt[i] = L.SB[i];
+  }
+  __syncthreads();
 
   // ---- Theorem 1 / Eq. (6): all sub-chains of the set together ----
   bool missed = false;
@@ -364,28 +385,12 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       if (lane == 0) L.misc[0] = 1;
       break;
     }
-    // weights at the current H*: WP[e][h] = E + H* of h on e (hp term of a
-    // lower-ranked chain) + hpp weight; Pt[e][h] = hpp weight alone, where
-    // hpp weight = sum over higher-priority executors e2 of the core of
-    // E + spin() (H* if h busy-waits, else its epsilon sum)
+    // the weight changes of the last sweep become this sweep's view
     for (int e = lane; e < X; e += kWave) {
-      L.wmin[e] = C;
-      L.pmax[e] = -1;
-    }
-    __syncthreads();
-    for (int i = lane; i < X * C; i += kWave) {
-      const int e = i / C, h = i - e * C;
-      const uint32_t hpx = b.hpx_mask[x0 + e];
-      double p = 0.0;
-      for (uint32_t m = hpx; m; m &= m - 1) {
-        const int e2 = __ffs(m) - 1;
-        p += L.Ece[e2 * C + h] + (L.spinf[h] ? L.Hs[e2 * C + h] : L.epsce[e2 * C + h]);
-      }
-      const double wp = L.Ece[i] + L.Hs[i] + p;
-      if (wp != L.WP[i]) atomicMin(&L.wmin[e], h);
-      if (p != L.Pt[i]) atomicMax(&L.pmax[e], h);
-      L.WP[i] = wp;
-      L.Pt[i] = p;
+      L.wmin[e] = L.wmin[X + e];
+      L.pmax[e] = L.pmax[X + e];
+      L.wmin[X + e] = C;
+      L.pmax[X + e] = -1;
     }
     __syncthreads();
 
@@ -527,7 +532,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
           hsn = (o.bound == PAAM_BOUND_L3 ? L3 : fmin(S.L2[s], L3)) + S.eps[s];
         }
         double rn = S.cst[s] + hsn + (I0 + I1);
-        if (rn > L.cap[rho]) {
+        if (rn > L.Dd[rho] * capm) {
           rn = INFINITY;
           if (needL3) {
             // Lemma 3 at an unbounded window: unbounded iff an HP request of
@@ -536,7 +541,23 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
             hsn = (o.bound == PAAM_BOUND_L3 ? L3i : fmin(S.L2[s], L3i)) + S.eps[s];
           }
         }
-        if (hsn != hs_old) atomicAdd(&L.Hs[e * C + rho], hsn - hs_old);
+        if (hsn != hs_old) {
+          // H* of the chain on e enters its hp weight on e and, for a
+          // busy-waiting chain, the hp and hpp weights on the core's
+          // lower-priority executors
+          const double dh = hsn - hs_old;
+          atomicAdd(&L.WP[e * C + rho], dh);
+          atomicMin(&L.wmin[X + e], rho);
+          if (L.spinf[rho]) {
+            for (uint32_t m = (uint32_t)L.lpx[e]; m; m &= m - 1) {
+              const int e2 = __ffs(m) - 1;
+              atomicAdd(&L.WP[e2 * C + rho], dh);
+              atomicAdd(&L.Pt[e2 * C + rho], dh);
+              atomicMin(&L.wmin[X + e2], rho);
+              atomicMax(&L.pmax[X + e2], rho);
+            }
+          }
+        }
         if (rn != r) atomicAdd(&L.partial[rho], rn - r);
         S.info1[s] = (inf1 & ~kConv) | (rn == r ? kConv : 0);
         S.r[s] = rn;
@@ -563,7 +584,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     bool late = false;
     for (int rho = lane; rho < C; rho += kWave) {
       double R = L.partial[rho] + (double)(L.nrun[rho] - 1) * hop;
-      if (R > L.cap[rho]) R = INFINITY;
+      if (R > L.Dd[rho] * capm) R = INFINITY;
       L.partial[rho] = R;
       if (R > L.Dd[rho]) late = true;
       if (full && chain_R) chain_R[c0 + L.perm[rho]] = isinf(R) ? PAAM_INF : (int64_t)R;
@@ -846,7 +867,7 @@ size_t wave_search_bytes(const DevBatch &b) {
 
 size_t wave_lds_bytes(const DevBatch &b) {
   const size_t Cm = b.max_C, Xm = b.max_X, NAm = b.max_NA > 0 ? b.max_NA : 1;
-  return 8 * (5 * Cm + 3 * NAm * Cm + 5 * Xm * Cm) + 4 * (4 * Cm + 2 * NAm * Cm + 2 * Xm + 16);
+  return 8 * (4 * Cm + 3 * NAm * Cm + 3 * Xm * Cm) + 4 * (4 * Cm + 2 * NAm * Cm + 5 * Xm + 16);
 }
 
 int launch_wcrt(const WcrtLaunch &L, void *stream) {
