@@ -791,13 +791,14 @@ static int grid_items(int64_t n_items, int waves_per_cu) {
   return (int)std::max<int64_t>(g, 1);
 }
 
-// Features grid: with LDS tables, as many waves per CU as the LDS holds (at
-// most 12, the register limit of the kernel); else 8.
+// Features grid: as many waves per CU as the kernel's registers allow (16:
+// it is built for four waves per SIMD), fewer when its LDS tables do not fit
+// that many.
 static int feat_grid(const paam_chainset *cs, int64_t n_items) {
-  int w = 8;
+  int w = 16;
   if (paam::feat_in_lds(cs->dev)) {
     const size_t per = paam::feat_wave_bytes(cs->dev);
-    w = (int)std::min<size_t>(12, (160 * 1024) / std::max<size_t>(per, 1));
+    w = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(per, 1));
     w = std::max(w, 1);
   }
   return grid_items(n_items, w);
@@ -959,7 +960,9 @@ paam_status paam_mlp_adam_step(float *d_params, uint16_t *d_packed, float *d_m, 
   return PAAM_OK;
 }
 
-// Candidates scored per chunk: at most 2^24 feature rows.
+// Sets scored per chunk: at most 2^24 feature rows (1.6 GB).  Larger chunks
+// of 256-chain sets (more waves in flight) measured slower: their per-wave
+// feature tables no longer stay in the caches.
 static int64_t score_chunk_sets(const paam_chainset *cs, const paam_search_opts *o) {
   const int64_t per = (int64_t)o->n_cand * std::max(cs->dev.max_C, 1);
   int64_t n = ((int64_t)1 << 24) / per;

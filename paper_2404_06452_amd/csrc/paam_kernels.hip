@@ -136,6 +136,7 @@ constexpr int kMaxIter = 1 << 20;
 // info1 bits of a sub-chain: accelerator mask in bits 0-7
 constexpr int kNeedL3 = 1 << 8;  // H* follows Lemma 3 at the current window
 constexpr int kConv = 1 << 9;    // last evaluation changed nothing
+constexpr int kHasP = 1 << 10;   // the executor has higher-priority executors on its core
 
 // Analyses one set under the uploaded priorities and writes its outputs.
 // Called by all 64 lanes of a wave.
@@ -341,7 +342,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     S.A0[s] = A0;
     S.eps[s] = eps;
     S.info0[s] = rho | (e << 16);
-    S.info1[s] = accm | (needL3 ? kNeedL3 : 0);
+    S.info1[s] = accm | (needL3 ? kNeedL3 : 0) | (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
   }
   __syncthreads();
   // suffix maximum of blocking candidates per executor, lowest priority up
@@ -417,16 +418,19 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       const int i = ib + lane;
       const bool valid = i < nact;
       int s = 0, rho = 0, e = 0, inf1 = 0;
-      double r = 0.0;
+      double r = 0.0, hs_old = 0.0, cst = 0.0;
       if (valid) {
+        // every per-sub-chain load the evaluation needs, issued together
         s = S.alist[i];
         const int i0 = S.info0[s];
         rho = i0 & 0xffff;
         e = i0 >> 16;
         inf1 = S.info1[s];
         r = S.r[s];
+        hs_old = S.hs[s];
+        cst = S.cst[s];
       }
-      const bool hasP = valid && b.hpx_mask[x0 + e] != 0;
+      const bool hasP = (inf1 & kHasP) != 0;
       // the loop bound is the same on every lane: keep it in a scalar register
       const int hend = __builtin_amdgcn_readfirstlane(wave_max_int(valid ? (hasP ? C : rho) : 0));
       const bool needL3 = (inf1 & kNeedL3) != 0;
@@ -525,13 +529,12 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         }
       }
       if (valid) {
-        const double hs_old = S.hs[s];
         double hsn = hs_old;
         if (needL3) {
           const double L3 = S.A0[s] + l3;
           hsn = (o.bound == PAAM_BOUND_L3 ? L3 : fmin(S.L2[s], L3)) + S.eps[s];
         }
-        double rn = S.cst[s] + hsn + (I0 + I1);
+        double rn = cst + hsn + (I0 + I1);
         if (rn > L.Dd[rho] * capm) {
           rn = INFINITY;
           if (needL3) {

@@ -25,6 +25,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // totals by lookup (O(C (X + NA)) per candidate instead of O(C^2 X)).
 constexpr int kMaxGroup = 16;
 constexpr int kScanC = 64;  // sets with more chains use the prefix-scan schedule
+constexpr int kFwd = 9;     // numerators of a chain from the prefix-scan schedule's forward pass
+// wave-uniform running totals of the prefix-scan schedule, in LDS: forward
+// (4 per executor, 4 per accelerator) and backward (3 and 3)
+constexpr int kScanCarry = 7 * (kMaxExec + kMaxAccel);
 
 // Per-wave tables: a set's order-independent totals (built once per set), the
 // walk state, and the per-candidate ranks, bucket levels and scans.
@@ -35,9 +39,7 @@ struct FeatTables {
   int64_t *Ahat, *Amax, *qA;                               // [Cm][NA]
   int64_t *setv;                                           // [8] set-level sums
   int64_t *colw;                                           // [2][Xm] column totals of hpp weights
-  int64_t *PS;                                             // [6][Xm][Cm+1] rank scans per executor
-  int64_t *PA;                                             // [4][NAm][Cm+1] rank scans per accelerator
-  int64_t *UB;                                             // [NAm][Cm] users' A* max, then within-level suffix max
+  int64_t *fwd;                                            // [Cm][kFwd] forward-pass numerators by rank
   int32_t *inv;                                            // [2][Cm] RM inversions above / below
   int32_t *S, *dl, *ncb, *mine, *uses, *spin;              // [Cm]
   int32_t *runs;                                           // [Cm][X]
@@ -52,7 +54,7 @@ struct FeatTables {
 __host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
   const size_t C = Cm, CX = (size_t)Cm * Xm, CA = (size_t)Cm * NAm;
   const size_t G = Cm > 64 ? (size_t)Cm : 64;
-  const size_t scan = Cm > kScanC ? 6 * (size_t)Xm * (C + 1) + 4 * (size_t)NAm * (C + 1) + CA : 0;
+  const size_t scan = Cm > kScanC ? (size_t)kFwd * C : 0;
   const size_t n64 = 8 * C + 9 * CX + 3 * CA + 8 + 2 * (size_t)Xm + scan;
   const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G * NAm + (Cm > kScanC ? 2 * C : 0);
   const size_t n16 = C + G;
@@ -86,11 +88,10 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.qA = d; d += CA;
   t.setv = d; d += 8;
   t.colw = d; d += 2 * (size_t)Xm;
-  t.PS = t.PA = t.UB = nullptr;
+  t.fwd = nullptr;
   if (Cm > kScanC) {
-    t.PS = d; d += 6 * (size_t)Xm * (C + 1);
-    t.PA = d; d += 4 * (size_t)NAm * (C + 1);
-    t.UB = d; d += CA;
+    t.fwd = d;
+    d += (size_t)kFwd * C;
   }
   int32_t *i = reinterpret_cast<int32_t *>(d);
   t.S = i; i += C;
@@ -466,140 +467,19 @@ __device__ __forceinline__ int64_t wave_incl_sum(int64_t v) {
   }
   return v;
 }
+__device__ __forceinline__ int64_t wave_incl_suffix_sum(int64_t v) {
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t n = __shfl_down(v, o);
+    if ((int)threadIdx.x + o < kWave) v += n;
+  }
+  return v;
+}
 __device__ __forceinline__ int64_t wave_incl_suffix_max(int64_t v) {
   for (int o = 1; o < kWave; o <<= 1) {
     const int64_t n = __shfl_down(v, o);
     if ((int)threadIdx.x + o < kWave) v = n > v ? n : v;
   }
   return v;
-}
-
-// K prefix sums at once: out[k][0] = 0 and out[k][r + 1] = sum of the k-th
-// value of ranks r' <= r (arrays of C + 1 at out + k * stride).  load(r, v)
-// fills v[0..K-1] for a rank below C; each 64-rank chunk issues all its loads
-// before any store.
-template <int K, class F>
-__device__ __forceinline__ void scan_prefix_k(int C, F load, int64_t *out, size_t stride) {
-  const int lane = threadIdx.x;
-  int64_t carry[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) carry[k] = 0;
-  for (int rb = 0; rb < C; rb += kWave) {
-    const int r = rb + lane;
-    int64_t v[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0;
-    if (r < C) load(r, v);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t x = wave_incl_sum(v[k]) + carry[k];
-      if (r < C) out[k * stride + r + 1] = x;
-      carry[k] = __shfl(x, kWave - 1);
-    }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k * stride] = 0;
-  }
-}
-
-// K suffix maxima (values >= 0): out[k][r] = max of the k-th value of ranks
-// r' >= r, out[k][C] = 0.
-template <int K, class F>
-__device__ __forceinline__ void scan_suffix_max_k(int C, F load, int64_t *out, size_t stride) {
-  const int lane = threadIdx.x;
-  int64_t carry[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) carry[k] = 0;
-  for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
-    const int r = rb + lane;
-    int64_t v[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0;
-    if (r < C) load(r, v);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      int64_t x = wave_incl_suffix_max(v[k]);
-      x = carry[k] > x ? carry[k] : x;
-      if (r < C) out[k * stride + r] = x;
-      carry[k] = __shfl(x, 0);
-    }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k * stride + C] = 0;
-  }
-}
-
-// Scans of one candidate (order in t.order: chain at each rank).  Per
-// executor: prefix sums of q, qa, E + A* + eps and "has a sub-chain" (HP
-// side), suffix maxima of the blocking candidates (LP side).  Per
-// accelerator: prefix sums of A-hat, its utilisation, users and positive
-// requests; then the users' largest A* in user order, turned into a suffix
-// maximum within each bucket level.  Ends synchronised.
-__device__ void feat_scans(const DevBatch &b, int64_t set, FeatTables &t) {
-  const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
-  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
-  const int64_t a0 = b.set_accel_off[set];
-  const int NA = (int)(b.set_accel_off[set + 1] - a0);
-  const int NAm = NA > 0 ? NA : 1;
-  const size_t Cp = (size_t)C + 1;
-  const int32_t *ord = t.order;
-  const size_t stride = (size_t)X * Cp;
-  for (int e = 0; e < X; ++e) {
-    int64_t *P = t.PS + (size_t)e * Cp;
-    scan_prefix_k<4>(C, [&](int r, int64_t *v) {
-      const int i = ord[r] * X + e;
-      v[0] = t.q[i];
-      v[1] = t.qa[i];
-      v[2] = t.Ece[i] + t.Acce[i] + t.epce[i];
-      v[3] = t.runs[i] > 0;
-    }, P, stride);
-    scan_suffix_max_k<2>(C, [&](int r, int64_t *v) {
-      const int i = ord[r] * X + e;
-      v[0] = t.bl[i];
-      v[1] = t.bS[i];
-    }, P + 4 * stride, stride);
-  }
-  const size_t astride = (size_t)NAm * Cp;
-  for (int a = 0; a < NA; ++a) {
-    scan_prefix_k<4>(C, [&](int r, int64_t *v) {
-      const int i = ord[r] * NAm + a;
-      v[0] = t.Ahat[i];
-      v[1] = t.qA[i];
-      v[2] = t.dca[i] > 0;
-      v[3] = t.Ahat[i] > 0;
-    }, t.PA + (size_t)a * Cp, astride);
-  }
-  __syncthreads();
-  for (int a = 0; a < NA; ++a) {
-    const int64_t *PU = t.PA + (size_t)(2 * NAm + a) * Cp;  // users ranked above each rank
-    int64_t *U = t.UB + (size_t)a * C;
-    for (int r = threadIdx.x; r < C; r += kWave) {
-      const int h = ord[r];
-      if (t.dca[h * NAm + a] > 0) U[PU[r]] = t.Amax[h * NAm + a];
-    }
-    __syncthreads();
-    // suffix maximum within each bucket level (level of user u: u * n / m)
-    const int64_t m = PU[C];
-    const int64_t nb = b.buckets[a0 + a];
-    int64_t carry = 0, carry_lev = -1;
-    for (int64_t ub = m > 0 ? ((m - 1) / kWave) * kWave : -1; ub >= 0; ub -= kWave) {
-      const int64_t uu = ub + threadIdx.x;
-      const int64_t lev = uu < m ? (uu * nb) / m : -2;
-      int64_t v = uu < m ? U[uu] : 0;
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int64_t nv = __shfl_down(v, o);
-        const int64_t nl = __shfl_down(lev, o);
-        if ((int)threadIdx.x + o < kWave && nl == lev) v = nv > v ? nv : v;
-      }
-      if (lev == carry_lev) v = carry > v ? carry : v;
-      if (uu < m) U[uu] = v;
-      carry = __shfl(v, 0);
-      carry_lev = __shfl(lev, 0);
-    }
-    __syncthreads();
-  }
 }
 
 // RM inversion counts of every chain (t.inv) under the order in t.rank:
@@ -655,77 +535,235 @@ __device__ void feat_inversions(const FeatTables &t, int C, int pa, int pb, bool
   __syncthreads();
 }
 
-// Prefix-scan schedule: chain c under the candidate whose scans feat_scans wrote.
-__device__ void feat_chain_scan(const DevBatch &b, int64_t set, const FeatTables &t, int c,
-                                uint16_t *row) {
+// Prefix-scan schedule for one candidate (order in t.order, inversion
+// counts in t.inv): lane r of each 64-rank chunk holds the chain at rank r.
+// A forward pass over the chunks (ranks ascending) turns wave-wide prefix
+// sums into every chain's higher-priority totals per executor (q, q_acc,
+// E + A* + eps, chains with a sub-chain) and per accelerator (A-hat, its
+// utilisation, users, positive requests); a backward pass (ranks descending)
+// turns suffix maxima and counts into the lower-priority terms, and the
+// same-bucket blocking into a suffix maximum segmented by bucket level (the
+// level of a rank, u * n / m with u the users ranked above it, never
+// decreases down the order).  Running totals between chunks sit in carry
+// (LDS); the forward numerators of a rank wait in t.fwd.  Row c of rows
+// receives chain c's 48 features.  Ends synchronised.
+__device__ void feat_candidate_scan(const DevBatch &b, int64_t set, const FeatTables &t,
+                                    int64_t *carry, uint16_t *rows) {
+  const int lane = threadIdx.x;
   const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
   const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
   const int64_t a0 = b.set_accel_off[set];
   const int NA = (int)(b.set_accel_off[set + 1] - a0);
   const int NAm = NA > 0 ? NA : 1;
-  const size_t Cp = (size_t)C + 1;
-  const int rho = t.rank[c];
-  const uint32_t uses = (uint32_t)t.uses[c];
-  FeatNums f;
-  f.n19 = t.inv[c];
-  f.n20 = t.inv[C + c];
-  int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0;
-  int64_t n25 = 0, n29 = 0;
-  const size_t stride = (size_t)X * Cp;
-  for (int e = 0; e < X; ++e) {
-    const int64_t rce = t.runs[c * X + e];
-    const int64_t *P = t.PS + (size_t)e * Cp;
-    const int64_t sq = P[rho], sqa = P[stride + rho], scar = P[2 * stride + rho];
-    const int64_t nhp = P[3 * stride + rho];
-    const int64_t nlp = P[3 * stride + C] - P[3 * stride + rho + 1];
-    const int64_t mbl = P[4 * stride + rho + 1], mbs = P[5 * stride + rho + 1];
-    n_carry += rce * 2 * scar;
-    n_bp += rce * mbl;
-    n_bs += rce * mbs;
-    if (rce > 0) {
-      q21 += sq;
-      q22 += sqa;
-      q24 = sq + sqa > q24 ? sq + sqa : q24;
-      n25 += nhp;
-      n29 += nlp;
-      m28 = mbs > m28 ? mbs : m28;
+  const int32_t *ord = t.order;
+  int64_t *cf = carry;                 // forward: [X][4], then [NA][4]
+  int64_t *cb = carry + 4 * (X + NA);  // backward: [X][3], then [NA][3]
+  for (int k = lane; k < 4 * (X + NA); k += kWave) cf[k] = 0;
+  for (int k = lane; k < 3 * (X + NA); k += kWave) cb[k] = (k >= 3 * X && (k - 3 * X) % 3 == 2) ? -1 : 0;
+  __syncthreads();
+
+  // ---- forward pass
+  for (int rb = 0; rb < C; rb += kWave) {
+    const int r = rb + lane;
+    const bool ok = r < C;
+    const int c = ok ? ord[r] : 0;
+    const uint32_t uses = ok ? (uint32_t)t.uses[c] : 0u;
+    int64_t n_carry = 0, q21 = 0, q22 = 0, q24 = 0, n25 = 0;
+    for (int e = 0; e < X; ++e) {
+      int64_t vq = 0, vqa = 0, vcar = 0, rce = 0;
+      if (ok) {
+        const int i = c * X + e;
+        vq = t.q[i];
+        vqa = t.qa[i];
+        vcar = t.Ece[i] + t.Acce[i] + t.epce[i];
+        rce = t.runs[i];
+      }
+      const int64_t vh = rce > 0 ? 1 : 0;
+      const int64_t *cy = cf + 4 * e;
+      const int64_t iq = wave_incl_sum(vq), iqa = wave_incl_sum(vqa);
+      const int64_t ic = wave_incl_sum(vcar), ih = wave_incl_sum(vh);
+      const int64_t sq = cy[0] + iq - vq, sqa = cy[1] + iqa - vqa;
+      const int64_t scar = cy[2] + ic - vcar, nhp = cy[3] + ih - vh;
+      n_carry += rce * 2 * scar;
+      if (rce > 0) {
+        q21 += sq;
+        q22 += sqa;
+        q24 = sq + sqa > q24 ? sq + sqa : q24;
+        n25 += nhp;
+      }
+      const int64_t tq = __shfl(iq, kWave - 1), tqa = __shfl(iqa, kWave - 1);
+      const int64_t tc = __shfl(ic, kWave - 1), th = __shfl(ih, kWave - 1);
+      __syncthreads();
+      if (lane == 0) {
+        cf[4 * e] += tq;
+        cf[4 * e + 1] += tqa;
+        cf[4 * e + 2] += tc;
+        cf[4 * e + 3] += th;
+      }
     }
+    int64_t n_acc = 0, q33 = 0, n36 = 0, f37 = 0;
+    for (int a = 0; a < NA; ++a) {
+      int64_t vA = 0, vqA = 0, vu = 0;
+      if (ok) {
+        const int i = c * NAm + a;
+        vA = t.Ahat[i];
+        vqA = t.qA[i];
+        vu = t.dca[i] > 0 ? 1 : 0;
+      }
+      const int64_t vp = vA > 0 ? 1 : 0;
+      const int64_t *cy = cf + 4 * (X + a);
+      const int64_t iA = wave_incl_sum(vA), iqA = wave_incl_sum(vqA);
+      const int64_t iu = wave_incl_sum(vu), ip = wave_incl_sum(vp);
+      if ((uses >> a) & 1u) {
+        n_acc += 2 * (int64_t)t.nra[c * NAm + a] * (cy[0] + iA - vA);
+        q33 += cy[1] + iqA - vqA;
+        n36 += cy[2] + iu - vu;
+        f37 |= (cy[3] + ip - vp) > 0 ? 1 : 0;
+      }
+      const int64_t tA = __shfl(iA, kWave - 1), tqA = __shfl(iqA, kWave - 1);
+      const int64_t tu = __shfl(iu, kWave - 1), tp = __shfl(ip, kWave - 1);
+      __syncthreads();
+      if (lane == 0) {
+        cf[4 * (X + a)] += tA;
+        cf[4 * (X + a) + 1] += tqA;
+        cf[4 * (X + a) + 2] += tu;
+        cf[4 * (X + a) + 3] += tp;
+      }
+    }
+    if (ok) {
+      int64_t *w = t.fwd + (size_t)r * kFwd;
+      w[0] = n_carry;
+      w[1] = q21;
+      w[2] = q22;
+      w[3] = q24;
+      w[4] = n25;
+      w[5] = n_acc;
+      w[6] = q33;
+      w[7] = n36;
+      w[8] = f37;
+    }
+    __syncthreads();
   }
-  f.q21 = q21; f.q22 = q22; f.q24 = q24; f.n_carry = n_carry; f.n_bp = n_bp; f.n_bs = n_bs;
-  f.m28 = m28; f.n25 = n25; f.n29 = n29;
-  hpp_terms(t, c, X, f);
-  int64_t n_acc = 0, q33 = 0, n_bacc = 0, n36 = 0, f37 = 0;
-  double f35 = 0.0;
-  const size_t astride = (size_t)NAm * Cp;
-  for (int a = 0; a < NA; ++a) {
-    if (!((uses >> a) & 1u)) continue;
-    const int64_t *P = t.PA + (size_t)a * Cp;
-    const int64_t u = P[2 * astride + rho];  // users ranked above c
-    const int64_t m = P[2 * astride + C];
-    const int64_t nb = b.buckets[a0 + a];
-    const int64_t lev = (u * nb) / m;
-    n_acc += 2 * (int64_t)t.nra[c * NAm + a] * P[rho];
-    q33 += P[astride + rho];
-    n36 += u;
-    f37 |= P[3 * astride + rho] > 0;
-    const int64_t bacc = (u + 1 < m && ((u + 1) * nb) / m == lev) ? t.UB[(size_t)a * C + u + 1] : 0;
-    n_bacc += (int64_t)t.dca[c * NAm + a] * bacc;
-    const double lvr = fratio(lev, nb);
-    f35 = lvr > f35 ? lvr : f35;
+
+  // ---- backward pass
+  for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
+    const int r = rb + lane;
+    const bool ok = r < C;
+    const int c = ok ? ord[r] : 0;
+    const uint32_t uses = ok ? (uint32_t)t.uses[c] : 0u;
+    int64_t n_bp = 0, n_bs = 0, m28 = 0, n29 = 0;
+    for (int e = 0; e < X; ++e) {
+      int64_t vbl = 0, vbs = 0, rce = 0;
+      if (ok) {
+        const int i = c * X + e;
+        vbl = t.bl[i];
+        vbs = t.bS[i];
+        rce = t.runs[i];
+      }
+      const int64_t vh = rce > 0 ? 1 : 0;
+      const int64_t *cy = cb + 3 * e;
+      int64_t xbl = wave_incl_suffix_max(vbl), xbs = wave_incl_suffix_max(vbs);
+      xbl = cy[0] > xbl ? cy[0] : xbl;
+      xbs = cy[1] > xbs ? cy[1] : xbs;
+      const int64_t xh = wave_incl_suffix_sum(vh) + cy[2];
+      // values of the ranks below r: the next lane's, or the carry for lane 63
+      int64_t mbl = __shfl_down(xbl, 1), mbs = __shfl_down(xbs, 1), nlp = __shfl_down(xh, 1);
+      if (lane == kWave - 1) {
+        mbl = cy[0];
+        mbs = cy[1];
+        nlp = cy[2];
+      }
+      n_bp += rce * mbl;
+      n_bs += rce * mbs;
+      if (rce > 0) {
+        n29 += nlp;
+        m28 = mbs > m28 ? mbs : m28;
+      }
+      const int64_t nbl = __shfl(xbl, 0), nbs = __shfl(xbs, 0), nh = __shfl(xh, 0);
+      __syncthreads();
+      if (lane == 0) {
+        cb[3 * e] = nbl;
+        cb[3 * e + 1] = nbs;
+        cb[3 * e + 2] = nh;
+      }
+    }
+    int64_t n_bacc = 0;
+    double f35 = 0.0;
+    for (int a = 0; a < NA; ++a) {
+      const int64_t m = cf[4 * (X + a) + 2];  // users of the accelerator
+      if (m == 0) continue;                  // wave-uniform
+      const int64_t nb = b.buckets[a0 + a];
+      int64_t vu = 0, vA = 0;
+      if (ok) {
+        const int i = c * NAm + a;
+        vu = t.dca[i] > 0 ? 1 : 0;
+        vA = vu ? t.Amax[i] : 0;
+      }
+      const int64_t *cy = cb + 3 * (X + a);
+      const int64_t su = wave_incl_suffix_sum(vu) + cy[0];  // users at rank r or below
+      const int64_t key = ((m - su) * nb) / m;              // level of rank r
+      int64_t xv = vA;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t nv = __shfl_down(xv, o);
+        const int64_t nk = __shfl_down(key, o);
+        if (lane + o < kWave && nk == key) xv = nv > xv ? nv : xv;
+      }
+      if (key == cy[2]) xv = cy[1] > xv ? cy[1] : xv;
+      int64_t nv = __shfl_down(xv, 1), nk = __shfl_down(key, 1);
+      if (lane == kWave - 1) {
+        nv = cy[1];
+        nk = cy[2];
+      }
+      if ((uses >> a) & 1u) {
+        n_bacc += (int64_t)t.dca[c * NAm + a] * (nk == key ? nv : 0);
+        const double lvr = fratio(key, nb);
+        f35 = lvr > f35 ? lvr : f35;
+      }
+      const int64_t ns = __shfl(su, 0), nxv = __shfl(xv, 0), nxk = __shfl(key, 0);
+      __syncthreads();
+      if (lane == 0) {
+        cb[3 * (X + a)] = ns;
+        cb[3 * (X + a) + 1] = nxv;
+        cb[3 * (X + a) + 2] = nxk;
+      }
+    }
+    if (ok) {
+      const int64_t *w = t.fwd + (size_t)r * kFwd;
+      FeatNums f;
+      f.n19 = t.inv[c];
+      f.n20 = t.inv[C + c];
+      f.n_carry = w[0];
+      f.q21 = w[1];
+      f.q22 = w[2];
+      f.q24 = w[3];
+      f.n25 = w[4];
+      f.n_acc = w[5];
+      f.q33 = w[6];
+      f.n36 = w[7];
+      f.f37 = w[8];
+      f.n_bp = n_bp;
+      f.n_bs = n_bs;
+      f.m28 = m28;
+      f.n29 = n29;
+      f.n_bacc = n_bacc;
+      f.f35 = f35;
+      hpp_terms(t, c, X, f);
+      feat_write(b, set, t, c, r, f, rows + (size_t)c * 48);
+    }
+    __syncthreads();
   }
-  f.n_acc = n_acc; f.q33 = q33; f.n_bacc = n_bacc; f.n36 = n36; f.f37 = f37; f.f35 = f35;
-  feat_write(b, set, t, c, rho, f, row);
 }
 
 // Work item i: explicit pairs (one candidate each), or in range mode a run of
 // up to 64 consecutive candidates of one set.  Tables in LDS (kLds) or in the
 // wave's global scratch.
 template <bool kLds>
-__global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void features_kernel(FeatLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char *base = kLds ? lds_raw : L.scratch + (size_t)blockIdx.x * L.scratch_stride;
   const int NAmx = L.b.max_NA > 0 ? L.b.max_NA : 1;
   FeatTables t = carve_feat(base, L.b.max_C, L.b.max_X, NAmx);
+  __shared__ int64_t scan_carry[kScanCarry];
   const int lane = threadIdx.x;
   // grid-stride: the item index is wave-uniform by construction
   for (int64_t i = blockIdx.x; i < L.n_items; i += gridDim.x) {
@@ -776,12 +814,9 @@ __global__ __launch_bounds__(kWave) void features_kernel(FeatLaunch L) {
         cur = k;
         const int32_t pq = step ? swap_positions(L.seed, set, k, C) : 0;
         feat_inversions(t, C, pq & 0xffff, pq >> 16, step);
-        feat_scans(L.b, set, t);
         const int64_t o = out0 + (k - k0);
-        for (int c = lane; c < C; c += kWave)
-          feat_chain_scan(L.b, set, t, c, L.feat + ((size_t)o * L.row_stride + c) * 48);
+        feat_candidate_scan(L.b, set, t, scan_carry, L.feat + (size_t)o * L.row_stride * 48);
         if (lane == 0) L.count[o] = C;
-        __syncthreads();
       }
       continue;
     }
