@@ -67,11 +67,12 @@ __device__ __forceinline__ bool ratio_gt(double Ra, int64_t Da, double Rb, int64
 struct Lds {
   double2 *KR;                       // [C] (2T-1, 1/T up) of the chain at a rank
   double *Dd, *partial;              // [C] deadline, running end-to-end sum
-  double *Ahat, *amax, *Bacc;        // [NA][C]
+  double *Ahat, *Bacc;               // [NA][C] A-hat; a user's largest A*, then its Bacc
   double *WP, *Pt;                   // [X][C] hp+hpp weight (rank above), hpp weight (below)
   double *SB;                        // [X][C] blocking candidates, then staging of the first build
-  int32_t *perm, *rank, *nrun, *spinf;  // [C]
-  int32_t *level, *uses;             // [NA][C]
+  int32_t *rank;                     // [C] rank of a chain
+  int32_t *nrs;                      // [C] sub-chains of the chain at a rank | busy-waits << 16
+  int32_t *level;                    // [NA][C] bucket level of a user, -1 for a non-user
   int32_t *wmin, *pmax;              // [2][X] lowest rank whose WP changed, highest whose Pt
                                      // changed: as seen by this sweep, as recorded for the next
   int32_t *lpx;                      // [X] executors of the core with lower process priority
@@ -91,18 +92,14 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   l.Dd = d; d += Cm;
   l.partial = d; d += Cm;
   l.Ahat = d; d += NAm * Cm;
-  l.amax = d; d += NAm * Cm;
   l.Bacc = d; d += NAm * Cm;
   l.WP = d; d += Xm * Cm;
   l.Pt = d; d += Xm * Cm;
   l.SB = d; d += Xm * Cm;
   int32_t *i = reinterpret_cast<int32_t *>(d);
-  l.perm = i; i += Cm;
   l.rank = i; i += Cm;
-  l.nrun = i; i += Cm;
-  l.spinf = i; i += Cm;
+  l.nrs = i; i += Cm;
   l.level = i; i += NAm * Cm;
-  l.uses = i; i += NAm * Cm;
   l.wmin = i; i += 2 * Xm;
   l.pmax = i; i += 2 * Xm;
   l.lpx = i; i += Xm;
@@ -163,19 +160,17 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   // ---- chain tables in rank order (rank 0 = highest priority) ----
   for (int c = lane; c < C; c += kWave) {
     const int rho = b.rank0[c0 + c];
-    L.perm[rho] = c;
     L.rank[c] = rho;
     L.KR[rho] = make_double2(b.Kd[c0 + c], b.rcp[c0 + c]);
     const int64_t D = b.D[c0 + c];
     L.Dd[rho] = (double)D;
-    L.nrun[rho] = b.chain_nrun[c0 + c];
-    L.spinf[rho] = b.spin[c0 + c];
+    L.nrs[rho] = b.chain_nrun[c0 + c] | (b.spin[c0 + c] ? 1 << 16 : 0);
     L.partial[rho] = 0.0;
   }
   for (int i = lane; i < NA * C; i += kWave) {
     L.Ahat[i] = 0.0;
-    L.amax[i] = 0.0;
-    L.uses[i] = 0;
+    L.Bacc[i] = 0.0;
+    L.level[i] = -1;
   }
   for (int i = lane; i < X * C; i += kWave) {
     L.WP[i] = 0.0;
@@ -200,38 +195,46 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     const double As = scale_time(b.A[g0 + g], u) + 2.0 * (double)b.akappa[a0 + a];
     S.segAs[g] = As;
     atomicAdd(&L.Ahat[a * C + rho], As);
-    lds_max(&L.amax[a * C + rho], As);
-    L.uses[a * C + rho] = 1;
+    lds_max(&L.Bacc[a * C + rho], As);
+    L.level[a * C + rho] = 0;  // a user
   }
   __syncthreads();
 
-  // ---- buckets (Sec. IV-C): users of an accelerator by priority, rank r of m
-  //      in level floor(r*n/m); then the LP same-bucket maximum of Eq. (3) ----
-  for (int rho = lane; rho < C; rho += kWave) {
-    for (int a = 0; a < NA; ++a) {
-      int lev = -1;
-      if (L.uses[a * C + rho]) {
-        int r = 0, m = 0;
-        for (int h = 0; h < C; ++h) {
-          const int us = L.uses[a * C + h];
-          m += us;
-          r += (us && h < rho) ? 1 : 0;
-        }
-        lev = (int)(((int64_t)r * b.buckets[a0 + a]) / m);
-      }
-      L.level[a * C + rho] = lev;
+  // ---- buckets (Sec. IV-C): the users of an accelerator in priority order,
+  //      user r of m in level floor(r*n/m); then, in place of a user's
+  //      largest A*, the largest A* of a lower-priority user of its level, the
+  //      blocking term of Eq. (3).  Levels never decrease down the order, so
+  //      one pass from the lowest rank up keeps a running maximum. ----
+  for (int a = 0; a < NA; ++a) {
+    int32_t *lv = L.level + a * C;
+    int m = 0;
+    for (int rb = 0; rb < C; rb += kWave) {
+      const int rho = rb + lane;
+      m += (int)__popcll(__ballot(rho < C && lv[rho] >= 0));
+    }
+    const int64_t n = b.buckets[a0 + a];
+    int r0 = 0;
+    for (int rb = 0; rb < C; rb += kWave) {
+      const int rho = rb + lane;
+      const bool us = rho < C && lv[rho] >= 0;
+      const unsigned long long bm = __ballot(us);
+      if (us) lv[rho] = (int)(((int64_t)(r0 + (int)__popcll(bm & ((1ull << lane) - 1ull))) * n) / m);
+      r0 += (int)__popcll(bm);
     }
   }
   __syncthreads();
-  for (int rho = lane; rho < C; rho += kWave) {
-    for (int a = 0; a < NA; ++a) {
-      double bm = 0.0;
-      const int lev = L.level[a * C + rho];
-      if (lev >= 0) {
-        for (int h = rho + 1; h < C; ++h)
-          if (L.level[a * C + h] == lev) bm = fmax(bm, L.amax[a * C + h]);
-      }
-      L.Bacc[a * C + rho] = bm;
+  for (int a = lane; a < NA; a += kWave) {
+    const int32_t *lv = L.level + a * C;
+    double *bx = L.Bacc + a * C;
+    int cur = -1;
+    double mx = 0.0;
+    for (int rho = C - 1; rho >= 0; --rho) {
+      const int lev = lv[rho];
+      if (lev < 0) continue;
+      const double own = bx[rho];
+      bx[rho] = lev == cur ? mx : 0.0;
+      mx = lev == cur ? fmax(mx, own) : own;
+      cur = lev;
     }
   }
   // highest-priority rank with a request of positive length on each
@@ -334,7 +337,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     // per chain and executor: E + H* (own executor's weight) in WP, and
     // E + spin() (H* if the chain busy-waits, else its epsilon sum) in Pt
     atomicAdd(&L.WP[e * C + rho], E + hs0);
-    atomicAdd(&L.Pt[e * C + rho], E + (L.spinf[rho] ? hs0 : eps));
+    atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
     S.r[s] = 0.0;
     S.hs[s] = hs0;
     S.cst[s] = E;  // blocking added below
@@ -551,7 +554,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
           const double dh = hsn - hs_old;
           atomicAdd(&L.WP[e * C + rho], dh);
           atomicMin(&L.wmin[X + e], rho);
-          if (L.spinf[rho]) {
+          if (L.nrs[rho] >> 16) {
             for (uint32_t m = (uint32_t)L.lpx[e]; m; m &= m - 1) {
               const int e2 = __ffs(m) - 1;
               atomicAdd(&L.WP[e2 * C + rho], dh);
@@ -573,7 +576,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       // deadline proves the miss
       bool miss = false;
       for (int rho = lane; rho < C; rho += kWave)
-        if (L.partial[rho] + (double)(L.nrun[rho] - 1) * hop > L.Dd[rho]) miss = true;
+        if (L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho]) miss = true;
       if (wave_any(miss)) {
         missed = true;
         break;
@@ -586,15 +589,20 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   if (!missed) {
     bool late = false;
     for (int rho = lane; rho < C; rho += kWave) {
-      double R = L.partial[rho] + (double)(L.nrun[rho] - 1) * hop;
+      double R = L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop;
       if (R > L.Dd[rho] * capm) R = INFINITY;
       L.partial[rho] = R;
       if (R > L.Dd[rho]) late = true;
-      if (full && chain_R) chain_R[c0 + L.perm[rho]] = isinf(R) ? PAAM_INF : (int64_t)R;
     }
     ok = !wave_any(late);
   }
   __syncthreads();
+  if (!missed && full && chain_R) {
+    for (int c = lane; c < C; c += kWave) {
+      const double R = L.partial[L.rank[c]];
+      chain_R[c0 + c] = isinf(R) ? PAAM_INF : (int64_t)R;
+    }
+  }
   if (lane == 0) {
     int32_t w = -1;
     int64_t wR = PAAM_INF;
@@ -870,7 +878,7 @@ size_t wave_search_bytes(const DevBatch &b) {
 
 size_t wave_lds_bytes(const DevBatch &b) {
   const size_t Cm = b.max_C, Xm = b.max_X, NAm = b.max_NA > 0 ? b.max_NA : 1;
-  return 8 * (4 * Cm + 3 * NAm * Cm + 3 * Xm * Cm) + 4 * (4 * Cm + 2 * NAm * Cm + 5 * Xm + 16);
+  return 8 * (4 * Cm + 2 * NAm * Cm + 3 * Xm * Cm) + 4 * (2 * Cm + NAm * Cm + 5 * Xm + 16);
 }
 
 int launch_wcrt(const WcrtLaunch &L, void *stream) {
