@@ -9,6 +9,8 @@ process sees a known sequence of launches:
 * ``score``  - network scores of every candidate (features + forward)
 * ``guided`` - scoring followed by the guided search (top 16, with fallback)
 * ``train``  - targets, then training steps of the ranking network
+* ``large``  - sets of 256 chains: the uploaded order's analysis, scores of
+  1,024 candidate orders per set, the exact confirmation of the top 32
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ def main(argv=None):
     from . import _paam, chaingen, surrogate
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("run", choices=("sweep", "search", "score", "guided", "train"))
+    ap.add_argument("run", choices=("sweep", "search", "score", "guided", "train", "large"))
     ap.add_argument("--sets", type=int, default=100_000)
     ap.add_argument("--cand", type=int, default=256)
     ap.add_argument("--util", type=int, default=1000)
@@ -54,6 +56,18 @@ def main(argv=None):
         tg = timed("targets", lambda: tr.targets(pairs))
         for r in range(args.repeat):
             timed("epoch %d" % r, lambda: tr.fit(pairs, tg.ratio[:args.samples], 1, 1e-3, seed + r))
+        return
+    if args.run == "large":
+        cs = chaingen.generate("large", args.sets)
+        dev = _paam.Chainset(cs, device="cuda:0")
+        net = _paam.Network(chaingen.mlp_init(1), device="cuda:0")
+        for r in range(args.repeat):
+            timed("RM analysis", lambda: _paam.wcrt(dev, full=False, util_permille=args.util))
+            sc = timed("score", lambda: _paam.score(dev, net, args.cand, seed,
+                                                    util_permille=args.util))
+            timed("guided search", lambda: _paam.search(dev, args.cand, seed, scores=sc,
+                                                        guided=True, top_k=32, fallback=False,
+                                                        util_permille=args.util))
         return
     cs = chaingen.generate("search", args.sets)
     dev = _paam.Chainset(cs, device="cuda:0")
