@@ -46,7 +46,7 @@ struct FeatTables {
   int32_t *dca, *nra;                                      // [Cm][NA]
   int32_t *hpx;                                            // [Xm]
   int32_t *order, *buf;                                    // [Cm], [64]
-  int32_t *levelg;                                         // [max(64, Cm)][NA]
+  int32_t *ordg;                                           // [max(64, Cm)] chain at each rank, per candidate of a pass
   int16_t *rank;                                           // [Cm]
   int16_t *rankg;                                          // [max(64, Cm)]
 };
@@ -56,7 +56,7 @@ __host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
   const size_t G = Cm > 64 ? (size_t)Cm : 64;
   const size_t scan = Cm > kScanC ? (size_t)kFwd * C : 0;
   const size_t n64 = 8 * C + 9 * CX + 3 * CA + 8 + 2 * (size_t)Xm + scan;
-  const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G * NAm + (Cm > kScanC ? 2 * C : 0);
+  const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G + (Cm > kScanC ? 2 * C : 0);
   const size_t n16 = C + G;
   return ((8 * n64 + 4 * n32 + 2 * n16) + 15) & ~(size_t)15;
 }
@@ -106,7 +106,7 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.hpx = i; i += Xm;
   t.order = i; i += C;
   t.buf = i; i += 64;
-  t.levelg = i; i += G * NAm;
+  t.ordg = i; i += G;
   t.inv = nullptr;
   if (Cm > kScanC) {
     t.inv = i;
@@ -382,81 +382,6 @@ __device__ __forceinline__ void hpp_terms(const FeatTables &t, int c, int X, Fea
   f.q_hpp = q;
 }
 
-// Direct schedule: chain c under the candidate with ranks rk and bucket
-// levels lv, summing over the other chains.
-__device__ void feat_chain(const DevBatch &b, int64_t set, const FeatTables &t, const int16_t *rk,
-                           const int32_t *lv, int c, uint16_t *row) {
-  const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
-  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
-  const int64_t a0 = b.set_accel_off[set];
-  const int NA = (int)(b.set_accel_off[set + 1] - a0);
-  const int NAm = NA > 0 ? NA : 1;
-  const int rho = rk[c];
-  const uint32_t uses = (uint32_t)t.uses[c];
-  FeatNums f;
-  rm_inversions(t, rk, C, c, rho, f);
-  int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0;
-  int64_t n25 = 0, n29 = 0;
-  for (int e = 0; e < X; ++e) {
-    const int64_t rce = t.runs[c * X + e];
-    int64_t sq = 0, sqa = 0, scar = 0, mbl = 0, mbs = 0;
-    int nhp = 0, nlp = 0;
-    for (int h = 0; h < C; ++h) {
-      const int ih = h * X + e;
-      const int rh = rk[h];
-      if (rh < rho) {
-        sq += t.q[ih];
-        sqa += t.qa[ih];
-        scar += t.Ece[ih] + t.Acce[ih] + t.epce[ih];
-        nhp += t.runs[ih] > 0;
-      } else if (rh > rho) {
-        mbl = t.bl[ih] > mbl ? t.bl[ih] : mbl;
-        mbs = t.bS[ih] > mbs ? t.bS[ih] : mbs;
-        nlp += t.runs[ih] > 0;
-      }
-    }
-    n_carry += rce * 2 * scar;
-    n_bp += rce * mbl;
-    n_bs += rce * mbs;
-    if (rce > 0) {
-      q21 += sq;
-      q22 += sqa;
-      q24 = sq + sqa > q24 ? sq + sqa : q24;
-      n25 += nhp;
-      n29 += nlp;
-      m28 = mbs > m28 ? mbs : m28;
-    }
-  }
-  f.q21 = q21; f.q22 = q22; f.q24 = q24; f.n_carry = n_carry; f.n_bp = n_bp; f.n_bs = n_bs;
-  f.m28 = m28; f.n25 = n25; f.n29 = n29;
-  hpp_terms(t, c, X, f);
-  int64_t n_acc = 0, q33 = 0, n_bacc = 0, n36 = 0, f37 = 0;
-  double f35 = 0.0;
-  for (int a = 0; a < NA; ++a) {
-    if (!((uses >> a) & 1u)) continue;
-    const int lev = lv[c * NAm + a];
-    int64_t hpA = 0, bacc = 0;
-    for (int h = 0; h < C; ++h) {
-      const int ih = h * NAm + a;
-      const int rh = rk[h];
-      if (rh < rho) {
-        hpA += t.Ahat[ih];
-        q33 += t.qA[ih];
-        n36 += t.dca[ih] > 0;
-        f37 |= t.Ahat[ih] > 0;
-      } else if (rh > rho && t.dca[ih] > 0 && lv[ih] == lev) {
-        bacc = t.Amax[ih] > bacc ? t.Amax[ih] : bacc;
-      }
-    }
-    n_acc += 2 * (int64_t)t.nra[c * NAm + a] * hpA;
-    n_bacc += (int64_t)t.dca[c * NAm + a] * bacc;
-    const double lvr = fratio(lev, b.buckets[a0 + a]);
-    f35 = lvr > f35 ? lvr : f35;
-  }
-  f.n_acc = n_acc; f.q33 = q33; f.n_bacc = n_bacc; f.n36 = n36; f.f37 = f37; f.f35 = f35;
-  feat_write(b, set, t, c, rho, f, row);
-}
-
 // ---- prefix-scan schedule (sets of more than kScanC chains)
 
 // Wave-wide inclusive prefix sum and suffix maximum over 64 lanes.
@@ -533,6 +458,126 @@ __device__ void feat_inversions(const FeatTables &t, int C, int pa, int pb, bool
     t.inv[C + down] = b20;
   }
   __syncthreads();
+}
+
+// Sets of up to 64 chains: the ng candidates of a pass at once, lane
+// g*C + r holding the chain at rank r of candidate g (order in t.ordg, ranks
+// in t.rankg).  The scans of the prefix-scan schedule run segmented within
+// each candidate's C lanes and need no running totals: every chain's
+// higher-priority totals come from prefix sums, its lower-priority terms from
+// suffix maxima and counts, the same-bucket blocking term from a suffix
+// maximum segmented by bucket level.  Candidate g's rows start at
+// rows + g * row_stride * 48.
+__device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables &t, int C,
+                                int ng, uint16_t *rows, int row_stride) {
+  const int lane = threadIdx.x;
+  const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
+  const int64_t a0 = b.set_accel_off[set];
+  const int NA = (int)(b.set_accel_off[set + 1] - a0);
+  const int NAm = NA > 0 ? NA : 1;
+  const int g = lane / C, r = lane - g * C;
+  const bool ok = g < ng;
+  const int c = ok ? t.ordg[g * C + r] : 0;
+  const uint32_t uses = ok ? (uint32_t)t.uses[c] : 0u;
+  auto sum_up = [&](int64_t v) {
+    for (int o = 1; o < C; o <<= 1) {
+      const int64_t n = __shfl_up(v, o);
+      if (r >= o) v += n;
+    }
+    return v;
+  };
+  auto sum_down = [&](int64_t v) {
+    for (int o = 1; o < C; o <<= 1) {
+      const int64_t n = __shfl_down(v, o);
+      if (r + o < C) v += n;
+    }
+    return v;
+  };
+  auto max_down = [&](int64_t v) {
+    for (int o = 1; o < C; o <<= 1) {
+      const int64_t n = __shfl_down(v, o);
+      if (r + o < C) v = n > v ? n : v;
+    }
+    return v;
+  };
+  // the value of the next rank of the same candidate, 0 past the last
+  auto next = [&](int64_t v) {
+    const int64_t n = __shfl_down(v, 1);
+    return r + 1 < C ? n : (int64_t)0;
+  };
+  FeatNums f;
+  int64_t q21 = 0, q22 = 0, q24 = 0, n_carry = 0, n_bp = 0, n_bs = 0, m28 = 0, n25 = 0, n29 = 0;
+  for (int e = 0; e < X; ++e) {
+    int64_t vq = 0, vqa = 0, vcar = 0, rce = 0, vbl = 0, vbs = 0;
+    if (ok) {
+      const int i = c * X + e;
+      vq = t.q[i];
+      vqa = t.qa[i];
+      vcar = t.Ece[i] + t.Acce[i] + t.epce[i];
+      rce = t.runs[i];
+      vbl = t.bl[i];
+      vbs = t.bS[i];
+    }
+    const int64_t vh = rce > 0 ? 1 : 0;
+    const int64_t sq = sum_up(vq) - vq, sqa = sum_up(vqa) - vqa;
+    const int64_t scar = sum_up(vcar) - vcar, nhp = sum_up(vh) - vh;
+    const int64_t mbl = next(max_down(vbl)), mbs = next(max_down(vbs)), nlp = next(sum_down(vh));
+    n_carry += rce * 2 * scar;
+    n_bp += rce * mbl;
+    n_bs += rce * mbs;
+    if (rce > 0) {
+      q21 += sq;
+      q22 += sqa;
+      q24 = sq + sqa > q24 ? sq + sqa : q24;
+      n25 += nhp;
+      n29 += nlp;
+      m28 = mbs > m28 ? mbs : m28;
+    }
+  }
+  f.q21 = q21; f.q22 = q22; f.q24 = q24; f.n_carry = n_carry; f.n_bp = n_bp; f.n_bs = n_bs;
+  f.m28 = m28; f.n25 = n25; f.n29 = n29;
+  int64_t n_acc = 0, q33 = 0, n_bacc = 0, n36 = 0, f37 = 0;
+  double f35 = 0.0;
+  for (int a = 0; a < NA; ++a) {
+    int64_t vA = 0, vqA = 0, vu = 0, vmax = 0;
+    if (ok) {
+      const int i = c * NAm + a;
+      vA = t.Ahat[i];
+      vqA = t.qA[i];
+      vu = t.dca[i] > 0 ? 1 : 0;
+      vmax = vu ? t.Amax[i] : 0;
+    }
+    const int64_t vp = vA > 0 ? 1 : 0;
+    const int64_t iu = sum_up(vu);
+    const int64_t hpA = sum_up(vA) - vA, pqA = sum_up(vqA) - vqA, uab = iu - vu;
+    const int64_t pab = sum_up(vp) - vp;
+    const int64_t mu_ = __shfl(iu, g * C + C - 1 < kWave ? g * C + C - 1 : kWave - 1);
+    const int64_t m = mu_ > 0 ? mu_ : 1;  // users of the accelerator in this candidate's set
+    const int64_t nb = b.buckets[a0 + a];
+    const int64_t key = (uab * nb) / m;    // bucket level of rank r
+    int64_t xv = vmax;
+    for (int o = 1; o < C; o <<= 1) {
+      const int64_t nv = __shfl_down(xv, o);
+      const int64_t nk = __shfl_down(key, o);
+      if (r + o < C && nk == key) xv = nv > xv ? nv : xv;
+    }
+    const int64_t nv1 = __shfl_down(xv, 1), nk1 = __shfl_down(key, 1);
+    if ((uses >> a) & 1u) {
+      n_acc += 2 * (int64_t)t.nra[c * NAm + a] * hpA;
+      q33 += pqA;
+      n36 += uab;
+      f37 |= pab > 0 ? 1 : 0;
+      n_bacc += (int64_t)t.dca[c * NAm + a] * ((r + 1 < C && nk1 == key) ? nv1 : 0);
+      const double lvr = fratio(key, nb);
+      f35 = lvr > f35 ? lvr : f35;
+    }
+  }
+  f.n_acc = n_acc; f.q33 = q33; f.n_bacc = n_bacc; f.n36 = n36; f.f37 = f37; f.f35 = f35;
+  if (ok) {
+    rm_inversions(t, t.rankg + g * C, C, c, r, f);
+    hpp_terms(t, c, X, f);
+    feat_write(b, set, t, c, r, f, rows + ((size_t)g * row_stride + c) * 48);
+  }
 }
 
 // Prefix-scan schedule for one candidate (order in t.order, inversion
@@ -831,33 +876,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
         for (int c = lane; c < C; c += kWave) t.rankg[j * C + c] = t.rank[c];
         __syncthreads();
       }
-      // bucket levels (Sec. IV-C) of every (candidate, chain, accelerator)
+      // chain at each rank of every candidate of the pass
       for (int idx = lane; idx < ng * C; idx += kWave) {
         const int g = idx / C, c = idx - g * C;
-        const int16_t *rk = t.rankg + g * C;
-        const int rho = rk[c];
-        for (int a = 0; a < NA; ++a) {
-          int lev = -1;
-          if (t.dca[c * NAm + a] > 0) {
-            int r = 0, m = 0;
-            for (int h = 0; h < C; ++h) {
-              if (t.dca[h * NAm + a] > 0) {
-                ++m;
-                r += rk[h] < rho ? 1 : 0;
-              }
-            }
-            lev = (int)(((int64_t)r * L.b.buckets[a0 + a]) / m);
-          }
-          t.levelg[(g * C + c) * NAm + a] = lev;
-        }
+        t.ordg[g * C + t.rankg[g * C + c]] = c;
       }
       __syncthreads();
-      for (int idx = lane; idx < ng * C; idx += kWave) {
-        const int g = idx / C, c = idx - g * C;
-        const int64_t o = out0 + (kb - k0) + g;
-        feat_chain(L.b, set, t, t.rankg + g * C, t.levelg + g * C * NAm, c,
-                   L.feat + ((size_t)o * L.row_stride + c) * 48);
-      }
+      feat_group_scan(L.b, set, t, C, ng, L.feat + (size_t)(out0 + (kb - k0)) * L.row_stride * 48,
+                      L.row_stride);
       for (int g = lane; g < ng; g += kWave) L.count[out0 + (kb - k0) + g] = C;
       __syncthreads();
     }

@@ -47,13 +47,29 @@ def _check_features(cs, pairs, seed=SEED):
                                                for c, f in diff[:4]])
 
 
+# sets of up to 64 chains run the segmented scans of one pass's candidates;
+# "multi" has three accelerators with three bucket levels and overheads;
+# "mixed" holds sets on both sides of 64 chains in one batch
+VARIANTS = {
+    "multi": ("small", dict(n_accel=3, max_seg_per_cb=2, n_buckets=3, eps=391_000,
+                            kappa=129_180, eps_hop=391_000, chains=(3, 20))),
+    "mixed": ("large", dict(chains=(30, 90), n_accel=2, n_buckets=4, n_exec=6)),
+}
+
+
 @pytest.mark.parametrize("preset,n_sets,n_pairs,utils", [
     ("small_overheads", 20, 60, (1000, 250)),
     ("sweep", 30, 60, (100, 550, 950)),
     ("search", 20, 60, (1000, 50)),
+    ("multi", 20, 60, (1000, 300)),
+    ("mixed", 6, 24, (1000,)),
 ])
 def test_features_bit_exact(preset, n_sets, n_pairs, utils):
-    cs = chaingen.generate(preset, n_sets)
+    if preset in VARIANTS:
+        base, kw = VARIANTS[preset]
+        cs = chaingen.generate(chaingen.PRESETS[base].replace(**kw), n_sets)
+    else:
+        cs = chaingen.generate(preset, n_sets)
     _check_features(cs, _pairs(cs, n_pairs, 1, utils=utils))
 
 
@@ -216,12 +232,18 @@ MID = dict(chains=(65, 140), n_accel=3, max_seg_per_cb=2, n_buckets=5, eps=391_0
            kappa=129_180, eps_hop=391_000, n_exec=5)
 
 
-@pytest.mark.parametrize("preset,n_sets,n_cand", [("search", 12, 70), ("mid", 3, 150)])
+@pytest.mark.parametrize("preset,n_sets,n_cand", [("search", 12, 70), ("mid", 3, 150),
+                                                   ("mixed", 4, 80)])
 def test_score_candidates_equals_explicit_path(preset, n_sets, n_cand):
     # range mode walks each run of 64 candidates one swap at a time (updated
     # inversion counts on sets of more than 64 chains); the explicit path
     # computes every pair from scratch
-    params = chaingen.PRESETS["large"].replace(**MID) if preset == "mid" else preset
+    if preset == "mid":
+        params = chaingen.PRESETS["large"].replace(**MID)
+    elif preset in VARIANTS:
+        params = chaingen.PRESETS[VARIANTS[preset][0]].replace(**VARIANTS[preset][1])
+    else:
+        params = preset
     cs = chaingen.generate(params, n_sets)
     dev = _paam.Chainset(cs, device=DEV)
     net = _paam.Network(chaingen.mlp_init(5), device=DEV)
