@@ -82,7 +82,7 @@ struct Lds {
 struct Scratch {
   double *segAs, *segH;                    // [max_segs]
   double *r, *hs, *cst, *L2, *A0, *eps;    // [max_runs]
-  int32_t *info0, *info1, *alist;          // [max_runs]
+  int32_t *info, *alist;                   // [max_runs] packed sub-chain word, active list
 };
 
 __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
@@ -119,8 +119,7 @@ __device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs
   s.A0 = d; d += max_runs;
   s.eps = d; d += max_runs;
   int32_t *i = reinterpret_cast<int32_t *>(d);
-  s.info0 = i; i += max_runs;
-  s.info1 = i; i += max_runs;
+  s.info = i; i += max_runs;
   s.alist = i;
   return s;
 }
@@ -130,10 +129,16 @@ __device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs
 // reports set_sched = -1.
 constexpr int kMaxIter = 1 << 20;
 
-// info1 bits of a sub-chain: accelerator mask in bits 0-7
-constexpr int kNeedL3 = 1 << 8;  // H* follows Lemma 3 at the current window
-constexpr int kConv = 1 << 9;    // last evaluation changed nothing
-constexpr int kHasP = 1 << 10;   // the executor has higher-priority executors on its core
+// Packed word of a sub-chain: rank of its chain in bits 0-11 (fewer than
+// 4,096 chains per set), executor in bits 12-16, accelerator mask in bits
+// 17-24, then flags.  The compaction of a sweep reads only this word.
+constexpr int kRankMask = 0xfff;
+constexpr int kExecShift = 12;
+constexpr int kAccShift = 17;
+constexpr int kNeedL3 = 1 << 25;  // H* follows Lemma 3 at the current window
+constexpr int kHasP = 1 << 26;    // the executor has higher-priority executors on its core
+constexpr int kConv = 1 << 27;    // last evaluation changed nothing
+constexpr int kInf = 1 << 28;     // the bound is past the cap
 
 // Analyses one set under the uploaded priorities and writes its outputs.
 // Called by all 64 lanes of a wave.
@@ -344,8 +349,8 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     S.L2[s] = L2;
     S.A0[s] = A0;
     S.eps[s] = eps;
-    S.info0[s] = rho | (e << 16);
-    S.info1[s] = accm | (needL3 ? kNeedL3 : 0) | (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
+    S.info[s] = rho | (e << kExecShift) | (accm << kAccShift) | (needL3 ? kNeedL3 : 0) |
+                (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
   }
   __syncthreads();
   // suffix maximum of blocking candidates per executor, lowest priority up
@@ -359,8 +364,9 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   __syncthreads();
   // blocking by one callback of a lower priority chain on the executor
   for (int s = lane; s < nrun; s += kWave) {
-    const int rho = S.info0[s] & 0xffff;
-    const int e = S.info0[s] >> 16;
+    const int w = S.info[s];
+    const int rho = w & kRankMask;
+    const int e = (w >> kExecShift) & 31;
     S.cst[s] += rho + 1 < C ? L.SB[e * C + rho + 1] : 0.0;
   }
   __syncthreads();
@@ -405,10 +411,9 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       const int s = sb + lane;
       bool act = false;
       if (s < nrun) {
-        const int i0 = S.info0[s];
-        const int rho = i0 & 0xffff, e = i0 >> 16;
-        act = !isinf(S.r[s]) &&
-              (!(S.info1[s] & kConv) || rho > L.wmin[e] || rho < L.pmax[e]);
+        const int w = S.info[s];
+        const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
+        act = !(w & kInf) && (!(w & kConv) || rho > L.wmin[e] || rho < L.pmax[e]);
       }
       const unsigned long long m = __ballot(act);
       if (act) S.alist[nact + (int)__popcll(m & ((1ull << lane) - 1ull))] = s;
@@ -425,10 +430,9 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       if (valid) {
         // every per-sub-chain load the evaluation needs, issued together
         s = S.alist[i];
-        const int i0 = S.info0[s];
-        rho = i0 & 0xffff;
-        e = i0 >> 16;
-        inf1 = S.info1[s];
+        inf1 = S.info[s];
+        rho = inf1 & kRankMask;
+        e = (inf1 >> kExecShift) & 31;
         r = S.r[s];
         hs_old = S.hs[s];
         cst = S.cst[s];
@@ -437,7 +441,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       // the loop bound is the same on every lane: keep it in a scalar register
       const int hend = __builtin_amdgcn_readfirstlane(wave_max_int(valid ? (hasP ? C : rho) : 0));
       const bool needL3 = (inf1 & kNeedL3) != 0;
-      const int accm = inf1 & 0xff;
+      const int accm = (inf1 >> kAccShift) & 0xff;
       const double *wp = L.WP + e * C;
       const double *pt = L.Pt + e * C;
       double I0 = 0.0, I1 = 0.0, l3 = 0.0;
@@ -565,7 +569,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
           }
         }
         if (rn != r) atomicAdd(&L.partial[rho], rn - r);
-        S.info1[s] = (inf1 & ~kConv) | (rn == r ? kConv : 0);
+        S.info[s] = (inf1 & ~kConv) | (rn == r ? kConv : 0) | (isinf(rn) ? kInf : 0);
         S.r[s] = rn;
         S.hs[s] = hsn;
       }
@@ -867,7 +871,7 @@ __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
 
 size_t wave_scratch_bytes(const DevBatch &b) {
   size_t n = (size_t)b.max_segs * 2 * sizeof(double) + (size_t)b.max_runs * 6 * sizeof(double) +
-             (size_t)b.max_runs * 3 * sizeof(int32_t);
+             (size_t)b.max_runs * 2 * sizeof(int32_t);
   return (n + 255) & ~(size_t)255;
 }
 
