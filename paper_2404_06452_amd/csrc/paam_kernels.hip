@@ -344,8 +344,11 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     atomicAdd(&L.WP[e * C + rho], E + hs0);
     atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
     S.r[s] = 0.0;
+    // constant part of the recurrence: E, blocking (added below) and, when H*
+    // does not follow Lemma 3 during the iteration, H* itself; only the
+    // others keep H* as state
     S.hs[s] = hs0;
-    S.cst[s] = E;  // blocking added below
+    S.cst[s] = E + (needL3 ? 0.0 : hs0);
     S.L2[s] = L2;
     S.A0[s] = A0;
     S.eps[s] = eps;
@@ -434,7 +437,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         rho = inf1 & kRankMask;
         e = (inf1 >> kExecShift) & 31;
         r = S.r[s];
-        hs_old = S.hs[s];
+        if (inf1 & kNeedL3) hs_old = S.hs[s];
         cst = S.cst[s];
       }
       const bool hasP = (inf1 & kHasP) != 0;
@@ -571,7 +574,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         if (rn != r) atomicAdd(&L.partial[rho], rn - r);
         S.info[s] = (inf1 & ~kConv) | (rn == r ? kConv : 0) | (isinf(rn) ? kInf : 0);
         S.r[s] = rn;
-        S.hs[s] = hsn;
+        if (needL3) S.hs[s] = hsn;
       }
     }
     __syncthreads();
