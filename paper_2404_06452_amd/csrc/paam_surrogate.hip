@@ -941,7 +941,7 @@ __device__ __forceinline__ bf16x8 load_x8(const uint16_t *row, int k0, bool vali
 constexpr int kFwdBlock = 64;
 constexpr int kPqStride = NH + 8;  // padded row of the pooled tile (bank spread)
 
-__global__ __launch_bounds__(256) void forward_kernel(FwdLaunch L) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void forward_kernel(FwdLaunch L) {
   __shared__ __attribute__((aligned(16))) uint16_t W1s[NH * KP];
   __shared__ __attribute__((aligned(16))) uint16_t Pq[kFwdBlock * kPqStride];
   __shared__ float ysum[4][kFwdBlock];
@@ -961,36 +961,52 @@ __global__ __launch_bounds__(256) void forward_kernel(FwdLaunch L) {
   __syncthreads();
   for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int64_t base = blk * kFwdBlock;
-    // ---- layer 1 and pooling: 16 candidates per wave
+    // ---- layer 1 and pooling: 16 candidates per wave.  The row counts of
+    // the wave's candidates are read at once (one per lane), and the feature
+    // tile after the current one is loaded before the current tile's MFMAs.
+    int myrows = 0;
+    if (l < 16 && base + w * 16 + l < L.n) myrows = L.count[base + w * 16 + l];
+    myrows = myrows < 0 ? 0 : myrows;
+    auto load_tile = [&](int m, int r0, bf16x8 &t0, bf16x8 &t1) {
+      const int rows = __shfl(myrows, m);
+      const uint16_t *X = L.feat + (size_t)(base + w * 16 + m) * L.row_stride * NF;
+      const int r = r0 + li;
+      const bool rv = r < rows;
+      t0 = load_x8(X + (size_t)r * NF, 8 * lg, rv);
+      t1 = load_x8(X + (size_t)r * NF, 32 + 8 * lg, rv);
+    };
+    bf16x8 na0, na1;
+    load_tile(0, 0, na0, na1);
     for (int m = 0; m < 16; ++m) {
       const int mb = w * 16 + m;
-      const int64_t cand = base + mb;
-      int rows = 0;
-      if (cand < L.n) rows = L.count[cand];
-      rows = rows < 0 ? 0 : rows;
-      const uint16_t *X = L.feat + (size_t)cand * L.row_stride * NF;
+      const int rows = __shfl(myrows, m);
       float pool[16];
       for (int nt = 0; nt < 16; ++nt) pool[nt] = 0.0f;
-      for (int r0 = 0; r0 < rows; r0 += 16) {
-        const int r = r0 + li;
-        const bool rv = r < rows;
-        const bf16x8 a0 = load_x8(X + (size_t)r * NF, 8 * lg, rv);
-        const bf16x8 a1 = load_x8(X + (size_t)r * NF, 32 + 8 * lg, rv);
-        for (int nt = 0; nt < 16; ++nt) {
-          const int n = nt * 16 + li;
-          const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
-          const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
-          f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
-          float sacc = 0.0f;
-          for (int j = 0; j < 4; ++j) {
-            const int rr = r0 + 4 * lg + j;
-            const float z = acc[j] + bias1[nt];
-            sacc += (rr < rows && z > 0.0f) ? z : 0.0f;
-          }
-          pool[nt] += sacc;
+      for (int r0 = 0;; r0 += 16) {
+        const bf16x8 a0 = na0, a1 = na1;
+        if (r0 + 16 < rows) {
+          load_tile(m, r0 + 16, na0, na1);
+        } else if (m + 1 < 16) {
+          load_tile(m + 1, 0, na0, na1);
         }
+        if (r0 < rows) {
+          for (int nt = 0; nt < 16; ++nt) {
+            const int n = nt * 16 + li;
+            const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
+            const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
+            float sacc = 0.0f;
+            for (int j = 0; j < 4; ++j) {
+              const int rr = r0 + 4 * lg + j;
+              const float z = acc[j] + bias1[nt];
+              sacc += (rr < rows && z > 0.0f) ? z : 0.0f;
+            }
+            pool[nt] += sacc;
+          }
+        }
+        if (r0 + 16 >= rows) break;
       }
       for (int nt = 0; nt < 16; ++nt) {
         float sv = pool[nt];
