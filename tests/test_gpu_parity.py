@@ -115,6 +115,26 @@ def test_large_sets_sample(paam):
         compare(paam, cs, dev, opts, ("large", opts))
 
 
+def test_mixed_size_classes_in_one_batch(paam):
+    # chain counts from 8 to 130 in one upload: the analysis and the search
+    # launch once per size class (up to 16, 32, 64, 128, 256 chains), several
+    # accelerators with bucket levels and overheads
+    for ne, eps, util in ((6, 391_000, (0.02, 0.3)), (3, 0, (0.005, 0.05))):
+        params = chaingen.PRESETS["large"].replace(
+            chains=(8, 130), cbs=(2, 8), n_exec=ne, n_accel=3, max_seg_per_cb=2, n_buckets=4,
+            eps=eps, kappa=eps // 3, eps_hop=eps, util=util)
+        cs = chaingen.generate(params, 40)
+        _mixed_classes(paam, cs, (ne, eps))
+
+
+def _mixed_classes(paam, cs, tag):
+    dev = paam.Chainset(cs)
+    for opts in (dict(full=True), dict(full=False), dict(full=True, cap_mult=2),
+                 dict(full=True, blocking=1)):
+        note("mixed classes %s %s" % (tag, opts))
+        compare(paam, cs, dev, opts, ("mixed classes", tag, opts))
+
+
 def test_empty_and_degenerate_batches(paam):
     # a single one-callback chain, a chain with zero WCET, one executor
     sets = [

@@ -54,3 +54,11 @@ def test_search_matches_oracle_varied_sets(paam):
                                           eps=1, kappa=1, eps_hop=1)
     check(paam, chaingen.generate(p, 2000), 40, 99, blocking=1)
     check(paam, chaingen.generate(p, 2000), 40, 98, cap_mult=2)
+
+
+def test_search_matches_oracle_mixed_size_classes(paam):
+    # sets of 8-100 chains in one upload: one search launch per size class
+    p = chaingen.PRESETS["large"].replace(chains=(8, 100), cbs=(2, 6), n_exec=3, n_accel=2,
+                                          n_buckets=3, util=(0.002, 0.02), seed=95)
+    g = check(paam, chaingen.generate(p, 24), 12, 31)
+    print("found", (g["found"] >= 0).mean(), flush=True)
