@@ -281,8 +281,9 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
   __syncthreads();
 }
 
-__device__ __forceinline__ void put_feat(uint16_t *row, int f, double v) {
-  row[f] = bf16_rne((float)v);
+// Feature f of a row assembled in registers: two bfloat16 per 32-bit word.
+__device__ __forceinline__ void put_feat(uint32_t *w, int f, double v) {
+  w[f >> 1] |= (uint32_t)bf16_rne((float)v) << (16 * (f & 1));
 }
 
 // Order-dependent numerators of one chain under one candidate.
@@ -304,56 +305,63 @@ __device__ void feat_write(const DevBatch &b, int64_t set, const FeatTables &t, 
   const int64_t T = t.T[c], D = t.D[c];
   const int S = t.S[c];
   const int64_t own = t.Ec[c] + t.Acc[c] + t.epc[c] + (int64_t)(S - 1) * hop;
-  put_feat(row, 0, fratio(t.Ec[c], D));
-  put_feat(row, 1, fratio(t.Acc[c], D));
-  put_feat(row, 2, fratio(t.epc[c], D));
-  put_feat(row, 3, fratio((int64_t)(S - 1) * hop, D));
-  put_feat(row, 4, fratio(own, D));
-  put_feat(row, 5, fratio(t.Emax[c], D));
-  put_feat(row, 6, fratio(S, 16));
-  put_feat(row, 7, fratio(t.dl[c], 16));
-  put_feat(row, 8, fratio(t.ncb[c], 32));
-  put_feat(row, 9, fratio(__popc((uint32_t)t.mine[c]), X));
-  put_feat(row, 10, fratio(D, T));
-  put_feat(row, 11, fratio(T, (int64_t)1 << 30));
-  put_feat(row, 12, t.spin[c] ? 1.0 : 0.0);
-  put_feat(row, 13, fratio(t.qsum[c], kQ));
-  put_feat(row, 14, fratio(t.qasum[c], kQ));
-  put_feat(row, 15, fratio(rho, C));
-  put_feat(row, 16, fratio(C - 1 - rho, C));
-  put_feat(row, 17, rho == 0 ? 1.0 : 0.0);
-  put_feat(row, 18, rho == C - 1 ? 1.0 : 0.0);
-  put_feat(row, 19, fratio(f.n19, C));
-  put_feat(row, 20, fratio(f.n20, C));
-  put_feat(row, 21, fratio(f.q21, kQ));
-  put_feat(row, 22, fratio(f.q22, kQ));
-  put_feat(row, 23, fratio(f.n_carry, D));
-  put_feat(row, 24, fratio(f.q24, kQ));
-  put_feat(row, 25, fratio(f.n25, C));
-  put_feat(row, 26, fratio(f.n_bp, D));
-  put_feat(row, 27, fratio(f.n_bs, D));
-  put_feat(row, 28, fratio(f.m28, D));
-  put_feat(row, 29, fratio(f.n29, C));
-  put_feat(row, 30, fratio(f.n_hpp, D));
-  put_feat(row, 31, fratio(f.q_hpp, kQ));
-  put_feat(row, 32, fratio(f.n_acc, D));
-  put_feat(row, 33, fratio(f.q33, kQ));
-  put_feat(row, 34, fratio(f.n_bacc, D));
-  put_feat(row, 35, f.f35);
-  put_feat(row, 36, fratio(f.n36, C));
-  put_feat(row, 37, f.f37 ? 1.0 : 0.0);
-  put_feat(row, 38, fratio(t.setv[0], (int64_t)X * kQ));
-  put_feat(row, 39, fratio(t.setv[4], kQ));
-  put_feat(row, 40, fratio(t.setv[1], kQ));
-  put_feat(row, 41, fratio(C, 256));
-  put_feat(row, 42, fratio(X, 8));
-  put_feat(row, 43, fratio(NA, 8));
-  put_feat(row, 44, fratio(t.setv[3], T));
+  uint32_t w[24];
+#pragma unroll
+  for (int i = 0; i < 24; ++i) w[i] = 0u;
+  put_feat(w, 0, fratio(t.Ec[c], D));
+  put_feat(w, 1, fratio(t.Acc[c], D));
+  put_feat(w, 2, fratio(t.epc[c], D));
+  put_feat(w, 3, fratio((int64_t)(S - 1) * hop, D));
+  put_feat(w, 4, fratio(own, D));
+  put_feat(w, 5, fratio(t.Emax[c], D));
+  put_feat(w, 6, fratio(S, 16));
+  put_feat(w, 7, fratio(t.dl[c], 16));
+  put_feat(w, 8, fratio(t.ncb[c], 32));
+  put_feat(w, 9, fratio(__popc((uint32_t)t.mine[c]), X));
+  put_feat(w, 10, fratio(D, T));
+  put_feat(w, 11, fratio(T, (int64_t)1 << 30));
+  put_feat(w, 12, t.spin[c] ? 1.0 : 0.0);
+  put_feat(w, 13, fratio(t.qsum[c], kQ));
+  put_feat(w, 14, fratio(t.qasum[c], kQ));
+  put_feat(w, 15, fratio(rho, C));
+  put_feat(w, 16, fratio(C - 1 - rho, C));
+  put_feat(w, 17, rho == 0 ? 1.0 : 0.0);
+  put_feat(w, 18, rho == C - 1 ? 1.0 : 0.0);
+  put_feat(w, 19, fratio(f.n19, C));
+  put_feat(w, 20, fratio(f.n20, C));
+  put_feat(w, 21, fratio(f.q21, kQ));
+  put_feat(w, 22, fratio(f.q22, kQ));
+  put_feat(w, 23, fratio(f.n_carry, D));
+  put_feat(w, 24, fratio(f.q24, kQ));
+  put_feat(w, 25, fratio(f.n25, C));
+  put_feat(w, 26, fratio(f.n_bp, D));
+  put_feat(w, 27, fratio(f.n_bs, D));
+  put_feat(w, 28, fratio(f.m28, D));
+  put_feat(w, 29, fratio(f.n29, C));
+  put_feat(w, 30, fratio(f.n_hpp, D));
+  put_feat(w, 31, fratio(f.q_hpp, kQ));
+  put_feat(w, 32, fratio(f.n_acc, D));
+  put_feat(w, 33, fratio(f.q33, kQ));
+  put_feat(w, 34, fratio(f.n_bacc, D));
+  put_feat(w, 35, f.f35);
+  put_feat(w, 36, fratio(f.n36, C));
+  put_feat(w, 37, f.f37 ? 1.0 : 0.0);
+  put_feat(w, 38, fratio(t.setv[0], (int64_t)X * kQ));
+  put_feat(w, 39, fratio(t.setv[4], kQ));
+  put_feat(w, 40, fratio(t.setv[1], kQ));
+  put_feat(w, 41, fratio(C, 256));
+  put_feat(w, 42, fratio(X, 8));
+  put_feat(w, 43, fratio(NA, 8));
+  put_feat(w, 44, fratio(t.setv[3], T));
   const int64_t n_est = own + f.n_carry + f.n_bs + f.n_hpp + f.n_acc + f.n_bacc;
   const int64_t q_est = f.q21 + f.q22 + f.q_hpp + f.q33;
-  put_feat(row, 45, fratio(n_est, D));
-  put_feat(row, 46, fratio(n_est, D) + fratio(q_est, kQ));
-  put_feat(row, 47, fratio(t.Ec[c] + t.Acc[c], t.setv[2]));
+  put_feat(w, 45, fratio(n_est, D));
+  put_feat(w, 46, fratio(n_est, D) + fratio(q_est, kQ));
+  put_feat(w, 47, fratio(t.Ec[c] + t.Acc[c], t.setv[2]));
+  // the row (96 bytes, 16-byte aligned) in six 16-byte stores
+  uint4 *dst = reinterpret_cast<uint4 *>(row);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) dst[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
 }
 
 // Chains ranked above / below c that beat / trail it in period (RM inversions).
