@@ -480,14 +480,30 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
           l3 = fma(m0, l3on ? av0 : 0.0, l3);
           ++h;
         }
-        for (; h < e_mid; ++h) {
+        // one table read per term: the lane picks WP below its rank, Pt above
+        for (; h + 1 < e_mid; h += 2) {
+          const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
+          const double m0 = mu_term(r, q0.x, q0.y);
+          const double m1 = mu_term(r, q1.x, q1.y);
+          double w0 = (h < rho ? wp : pt)[h];
+          double w1 = (h + 1 < rho ? wp : pt)[h + 1];
+          w0 = h == rho ? 0.0 : w0;
+          w1 = h + 1 == rho ? 0.0 : w1;
+          const double av0 = ah[h], av1 = ah[h + 1];  // h + 1 < hend <= C: in bounds
+          I0 = fma(m0, w0, I0);
+          I1 = fma(m1, w1, I1);
+          l3 = fma(m0, (l3on && h < rho) ? av0 : 0.0, l3);
+          l3 = fma(m1, (l3on && h + 1 < rho) ? av1 : 0.0, l3);
+        }
+        if (h < e_mid) {
           const double2 q0 = L.KR[h];
           const double m0 = mu_term(r, q0.x, q0.y);
-          double w0 = h < rho ? wp[h] : pt[h];
+          double w0 = (h < rho ? wp : pt)[h];
           w0 = h == rho ? 0.0 : w0;
-          const double av0 = ah[h];  // h < hend <= C: in bounds
+          const double av0 = ah[h];
           I0 = fma(m0, w0, I0);
           l3 = fma(m0, (l3on && h < rho) ? av0 : 0.0, l3);
+          ++h;
         }
 #pragma unroll 2
         for (; h + 1 < hend; h += 2) {
