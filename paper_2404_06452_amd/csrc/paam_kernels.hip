@@ -461,16 +461,26 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         const int rhi = __builtin_amdgcn_readfirstlane(wave_max_int(valid ? rho : -1));
         const int e_lo = rlo < hend ? rlo : hend;
         const int e_mid = rhi + 1 < hend ? rhi + 1 : hend;
+        if (!wave_any(l3on)) {
+          // no lane of the chunk follows Lemma 3: hp weights only
 #pragma unroll 2
-        for (; h + 1 < e_lo; h += 2) {
-          const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
-          const double m0 = mu_term(r, q0.x, q0.y);
-          const double m1 = mu_term(r, q1.x, q1.y);
-          const double av0 = ah[h], av1 = ah[h + 1];
-          I0 = fma(m0, wp[h], I0);
-          I1 = fma(m1, wp[h + 1], I1);
-          l3 = fma(m0, l3on ? av0 : 0.0, l3);
-          l3 = fma(m1, l3on ? av1 : 0.0, l3);
+          for (; h + 1 < e_lo; h += 2) {
+            const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
+            I0 = fma(mu_term(r, q0.x, q0.y), wp[h], I0);
+            I1 = fma(mu_term(r, q1.x, q1.y), wp[h + 1], I1);
+          }
+        } else {
+#pragma unroll 2
+          for (; h + 1 < e_lo; h += 2) {
+            const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
+            const double m0 = mu_term(r, q0.x, q0.y);
+            const double m1 = mu_term(r, q1.x, q1.y);
+            const double av0 = ah[h], av1 = ah[h + 1];
+            I0 = fma(m0, wp[h], I0);
+            I1 = fma(m1, wp[h + 1], I1);
+            l3 = fma(m0, l3on ? av0 : 0.0, l3);
+            l3 = fma(m1, l3on ? av1 : 0.0, l3);
+          }
         }
         if (h < e_lo) {
           const double2 q0 = L.KR[h];
