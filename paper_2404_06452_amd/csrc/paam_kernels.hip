@@ -461,7 +461,8 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         const int rhi = __builtin_amdgcn_readfirstlane(wave_max_int(valid ? rho : -1));
         const int e_lo = rlo < hend ? rlo : hend;
         const int e_mid = rhi + 1 < hend ? rhi + 1 : hend;
-        if (!wave_any(l3on)) {
+        const bool anyl3 = wave_any(l3on);
+        if (!anyl3) {
           // no lane of the chunk follows Lemma 3: hp weights only
 #pragma unroll 2
           for (; h + 1 < e_lo; h += 2) {
@@ -491,6 +492,17 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
           ++h;
         }
         // one table read per term: the lane picks WP below its rank, Pt above
+        if (!anyl3) {
+          for (; h + 1 < e_mid; h += 2) {
+            const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
+            double w0 = (h < rho ? wp : pt)[h];
+            double w1 = (h + 1 < rho ? wp : pt)[h + 1];
+            w0 = h == rho ? 0.0 : w0;
+            w1 = h + 1 == rho ? 0.0 : w1;
+            I0 = fma(mu_term(r, q0.x, q0.y), w0, I0);
+            I1 = fma(mu_term(r, q1.x, q1.y), w1, I1);
+          }
+        }
         for (; h + 1 < e_mid; h += 2) {
           const double2 q0 = L.KR[h], q1 = L.KR[h + 1];
           const double m0 = mu_term(r, q0.x, q0.y);
