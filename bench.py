@@ -45,8 +45,8 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "e11cd53e2511def6bc4d633f1ee813efd0a6ccaa6af3f86a43d2e9ed1a9bb84c",
-           "bytes_per_launch": 15.20e9, "sets": 1_000_000, "waves_per_cu": 16}
+TRAFFIC = {"sha256": "a411f35c65e120634b25f1db2943945b77f201880184e9b238851829c3c7560c",
+           "bytes_per_launch": 15.18e9, "sets": 1_000_000, "waves_per_cu": 16}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
