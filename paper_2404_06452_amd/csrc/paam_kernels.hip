@@ -37,7 +37,7 @@ __device__ __forceinline__ double scale_time(int64_t x, int32_t u) {
   return (double)(u == 1000 ? x : (x * (int64_t)u) / 1000);
 }
 
-__device__ __forceinline__ void lds_max(double *p, double v) {
+__device__ __forceinline__ void atomic_max_nonneg(double *p, double v) {
   // non-negative doubles (and +inf) order like their bit patterns
   atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
 }
@@ -63,6 +63,11 @@ __device__ __forceinline__ bool ratio_gt(double Ra, int64_t Da, double Rb, int64
   return l > r;
 }
 
+// The blocking table ([X][C] doubles, used before the iteration only) sits
+// in LDS for sets of up to 512 chain-executor pairs, else in the wave's
+// global scratch, so that large sets keep more waves per CU.
+__host__ __device__ inline bool sb_in_scratch(int Cm, int Xm) { return (size_t)Cm * Xm > 512; }
+
 // LDS of one wave.  Tables by rank (0 = highest priority) with row stride C.
 struct Lds {
   double2 *KR;                       // [C] (2T-1, 1/T up) of the chain at a rank
@@ -70,6 +75,7 @@ struct Lds {
   double *Ahat, *Bacc;               // [NA][C] A-hat; a user's largest A*, then its Bacc
   double *WP, *Pt;                   // [X][C] hp+hpp weight (rank above), hpp weight (below)
   double *SB;                        // [X][C] blocking candidates, then staging of the first build
+                                     // (in the wave's global scratch for large tables)
   int32_t *rank;                     // [C] rank of a chain
   int32_t *nrs;                      // [C] sub-chains of the chain at a rank | busy-waits << 16
   int32_t *level;                    // [NA][C] bucket level of a user, -1 for a non-user
@@ -80,6 +86,7 @@ struct Lds {
 };
 
 struct Scratch {
+  double *SB;                              // [max_X][max_C] when not in LDS
   double *segAs, *segH;                    // [max_segs]
   double *r, *hs, *cst, *L2, *A0, *eps;    // [max_runs]
   int32_t *info, *alist;                   // [max_runs] packed sub-chain word, active list
@@ -95,7 +102,11 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   l.Bacc = d; d += NAm * Cm;
   l.WP = d; d += Xm * Cm;
   l.Pt = d; d += Xm * Cm;
-  l.SB = d; d += Xm * Cm;
+  l.SB = nullptr;
+  if (!sb_in_scratch(Cm, Xm)) {
+    l.SB = d;
+    d += Xm * Cm;
+  }
   int32_t *i = reinterpret_cast<int32_t *>(d);
   l.rank = i; i += Cm;
   l.nrs = i; i += Cm;
@@ -107,9 +118,14 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   return l;
 }
 
-__device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs) {
+__device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs, int Cm, int Xm) {
   Scratch s;
   double *d = reinterpret_cast<double *>(base);
+  s.SB = nullptr;
+  if (sb_in_scratch(Cm, Xm)) {
+    s.SB = d;
+    d += (size_t)Xm * Cm;
+  }
   s.segAs = d; d += max_segs;
   s.segH = d; d += max_segs;
   s.r = d; d += max_runs;
@@ -142,6 +158,8 @@ constexpr int kInf = 1 << 28;     // the bound is past the cap
 
 // Analyses one set under the uploaded priorities and writes its outputs.
 // Called by all 64 lanes of a wave.
+// kSbLds: the blocking table is in LDS (else in the wave's global scratch).
+template <bool kSbLds>
 __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t set, Lds &L,
                             Scratch &S, int8_t *set_sched, int32_t *set_worst,
                             int64_t *set_worst_R, int64_t *chain_R) {
@@ -161,6 +179,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   const bool full = o.full != 0;
   const double hop = (double)b.eps_hop[set];
   const double capm = (double)o.cap_mult;  // cap of a chain = capm * D
+  double *const SB = kSbLds ? L.SB : S.SB;
 
   // ---- chain tables in rank order (rank 0 = highest priority) ----
   for (int c = lane; c < C; c += kWave) {
@@ -180,7 +199,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   for (int i = lane; i < X * C; i += kWave) {
     L.WP[i] = 0.0;
     L.Pt[i] = 0.0;
-    L.SB[i] = 0.0;
+    SB[i] = 0.0;
   }
   for (int e = lane; e < X; e += kWave) {
     uint32_t m = 0;
@@ -200,7 +219,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     const double As = scale_time(b.A[g0 + g], u) + 2.0 * (double)b.akappa[a0 + a];
     S.segAs[g] = As;
     atomicAdd(&L.Ahat[a * C + rho], As);
-    lds_max(&L.Bacc[a * C + rho], As);
+    atomic_max_nonneg(&L.Bacc[a * C + rho], As);
     L.level[a * C + rho] = 0;  // a user
   }
   __syncthreads();
@@ -327,7 +346,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       }
       bmax = fmax(bmax, bj);
     }
-    lds_max(&L.SB[e * C + rho], bmax);
+    atomic_max_nonneg(&SB[e * C + rho], bmax);
     const bool needL3 =
         delta > 0 && (o.bound == PAAM_BOUND_L3 || (o.bound == PAAM_BOUND_MIN && delta >= 2));
     // H* of a sub-chain that does not need Lemma 3 during the iteration.  With
@@ -360,8 +379,8 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   for (int e = lane; e < X; e += kWave) {
     double m = 0.0;
     for (int rho = C - 1; rho >= 0; --rho) {
-      m = fmax(m, L.SB[e * C + rho]);
-      L.SB[e * C + rho] = m;
+      m = fmax(m, SB[e * C + rho]);
+      SB[e * C + rho] = m;
     }
   }
   __syncthreads();
@@ -370,7 +389,7 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     const int w = S.info[s];
     const int rho = w & kRankMask;
     const int e = (w >> kExecShift) & 31;
-    S.cst[s] += rho + 1 < C ? L.SB[e * C + rho + 1] : 0.0;
+    S.cst[s] += rho + 1 < C ? SB[e * C + rho + 1] : 0.0;
   }
   __syncthreads();
   // interference weights at the starting H*: WP[e][h] = E + H* of h on e (hp
@@ -382,12 +401,12 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
     const int e = i / C, h = i - e * C;
     double p = 0.0;
     for (uint32_t m = b.hpx_mask[x0 + e]; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
-    L.SB[i] = p;  // blocking candidates are dead
+    SB[i] = p;  // blocking candidates are dead
   }
   __syncthreads();
   for (int i = lane; i < X * C; i += kWave) {
-    L.WP[i] += L.SB[i];
-    L.Pt[i] = L.SB[i];
+    L.WP[i] += SB[i];
+    L.Pt[i] = SB[i];
   }
   __syncthreads();
 
@@ -671,18 +690,19 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
 
 __global__ void reset_counter(unsigned long long *counter) { *counter = 0ull; }
 
+template <bool kSbLds>
 __global__ __launch_bounds__(kWave) void wcrt_kernel(WcrtLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
   Scratch s = carve_scratch(L.scratch + (size_t)blockIdx.x * L.scratch_stride, L.b.max_segs,
-                            L.b.max_runs);
+                            L.b.max_runs, L.b.max_C, L.b.max_X);
   for (;;) {
     unsigned long long i = 0;
     if (threadIdx.x == 0) i = atomicAdd(L.counter, 1ull);
     i = __shfl(i, 0);
     if (i >= (unsigned long long)L.b.n_sets) break;
     const int64_t set = L.b.work_order[i];
-    analyse_set(L.b, L.o, set, l, s, L.set_sched, L.set_worst, L.set_worst_R, L.chain_R);
+    analyse_set<kSbLds>(L.b, L.o, set, l, s, L.set_sched, L.set_worst, L.set_worst_R, L.chain_R);
   }
 }
 
@@ -754,11 +774,12 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 // Plain: candidates 0, 1, ... in index order; the first feasible is the
 // smallest feasible k.  Guided: the top_k candidates by score in score order,
 // then (with fallback) the others in index order.
+template <bool kSbLds>
 __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
   unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
-  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs);
+  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs, L.b.max_C, L.b.max_X);
   SearchSlot q = carve_slot(wbase + L.analysis_stride, L.b.max_C);
   paam_wcrt_opts o = L.o.wcrt;
   o.full = 0;
@@ -801,7 +822,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
         }
         walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
         cur = k;
-        analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+        analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
         ++n_eval;
         int v = 0;
         if (threadIdx.x == 0) v = q.sched[0];  // written by lane 0 of analyse_set
@@ -822,7 +843,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
           }
           walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
           cur = k;
-          analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+          analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
           ++n_eval;
           int v = 0;
           if (threadIdx.x == 0) v = q.sched[0];
@@ -837,7 +858,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
       for (int k = 0; k < n_cand; ++k) {
         walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
         cur = k;
-        analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+        analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
         ++n_eval;
         int v = 0;
         if (threadIdx.x == 0) v = q.sched[0];
@@ -860,11 +881,12 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
 
 // Exact analysis of explicit (set, k, util_permille) candidates: every
 // chain's bound at cap_mult * D, reduced to the worst chain and its ratio.
+template <bool kSbLds>
 __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
   unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
-  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs);
+  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs, L.b.max_C, L.b.max_X);
   SearchSlot q = carve_slot(wbase + L.analysis_stride, L.b.max_C);
   // Grid-stride over the pairs: the item index derives from blockIdx only, so
   // it is wave-uniform by construction.  (With a lane-0 queue fetch, the path
@@ -890,7 +912,7 @@ __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
     paam_wcrt_opts o = L.o;
     o.full = 1;
     o.util_permille = (int32_t)u;
-    analyse_set(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+    analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
     if (threadIdx.x == 0) {
       const int w = q.worst[0];
       const int64_t wR = q.worst_R[0];
@@ -913,6 +935,7 @@ __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
 size_t wave_scratch_bytes(const DevBatch &b) {
   size_t n = (size_t)b.max_segs * 2 * sizeof(double) + (size_t)b.max_runs * 6 * sizeof(double) +
              (size_t)b.max_runs * 2 * sizeof(int32_t);
+  if (sb_in_scratch(b.max_C, b.max_X)) n += (size_t)b.max_X * b.max_C * sizeof(double);
   return (n + 255) & ~(size_t)255;
 }
 
@@ -923,7 +946,8 @@ size_t wave_search_bytes(const DevBatch &b) {
 
 size_t wave_lds_bytes(const DevBatch &b) {
   const size_t Cm = b.max_C, Xm = b.max_X, NAm = b.max_NA > 0 ? b.max_NA : 1;
-  return 8 * (4 * Cm + 2 * NAm * Cm + 3 * Xm * Cm) + 4 * (2 * Cm + NAm * Cm + 5 * Xm + 16);
+  const size_t sb = sb_in_scratch((int)Cm, (int)Xm) ? 0 : Xm * Cm;
+  return 8 * (4 * Cm + 2 * NAm * Cm + 2 * Xm * Cm + sb) + 4 * (2 * Cm + NAm * Cm + 5 * Xm + 16);
 }
 
 int launch_wcrt(const WcrtLaunch &L, void *stream) {
@@ -932,14 +956,20 @@ int launch_wcrt(const WcrtLaunch &L, void *stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   if (L.b.n_sets == 0) return 0;
-  hipLaunchKernelGGL(wcrt_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  if (sb_in_scratch(L.b.max_C, L.b.max_X))
+    hipLaunchKernelGGL(wcrt_kernel<false>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  else
+    hipLaunchKernelGGL(wcrt_kernel<true>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
 }
 
 int launch_candidates(const CandLaunch &L, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (L.n_pairs == 0) return 0;
-  hipLaunchKernelGGL(candidate_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  if (sb_in_scratch(L.b.max_C, L.b.max_X))
+    hipLaunchKernelGGL(candidate_kernel<false>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  else
+    hipLaunchKernelGGL(candidate_kernel<true>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
 }
 
@@ -949,7 +979,10 @@ int launch_search(const SearchLaunch &L, void *stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   if (L.b.n_sets == 0) return 0;
-  hipLaunchKernelGGL(search_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  if (sb_in_scratch(L.b.max_C, L.b.max_X))
+    hipLaunchKernelGGL(search_kernel<false>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  else
+    hipLaunchKernelGGL(search_kernel<true>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
 }
 
