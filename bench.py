@@ -45,8 +45,8 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "a411f35c65e120634b25f1db2943945b77f201880184e9b238851829c3c7560c",
-           "bytes_per_launch": 15.18e9, "sets": 1_000_000, "waves_per_cu": 16}
+TRAFFIC = {"sha256": "482aa273ceed1ba64fc5fd698ecd8d217a12c9f4f065627f2562e09cd841c651",
+           "bytes_per_launch": 15.16e9, "sets": 1_000_000, "waves_per_cu": 16}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
