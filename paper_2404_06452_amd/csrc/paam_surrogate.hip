@@ -35,7 +35,8 @@ constexpr int kScanCarry = 7 * (kMaxExec + kMaxAccel);
 struct FeatTables {
   int64_t *Ec, *Acc, *epc, *Emax, *qsum, *qasum, *T, *D;  // [Cm]
   int64_t *Ece, *Acce, *epce, *bl, *bS, *q, *qa;          // [Cm][X]
-  int64_t *hpn, *hpq;                                      // [Cm][X] OS-preemption numerators
+  int64_t *car;                                            // [Cm][X] E + A* + eps per chain and executor
+  int64_t *hppn, *hppq;                                    // [Cm] OS-preemption numerators of a chain
   int64_t *Ahat, *Amax, *qA;                               // [Cm][NA]
   int64_t *setv;                                           // [8] set-level sums
   int64_t *colw;                                           // [2][Xm] column totals of hpp weights
@@ -55,7 +56,7 @@ __host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
   const size_t C = Cm, CX = (size_t)Cm * Xm, CA = (size_t)Cm * NAm;
   const size_t G = Cm > 64 ? (size_t)Cm : 64;
   const size_t scan = Cm > kScanC ? (size_t)kFwd * C : 0;
-  const size_t n64 = 8 * C + 9 * CX + 3 * CA + 8 + 2 * (size_t)Xm + scan;
+  const size_t n64 = 10 * C + 8 * CX + 3 * CA + 8 + 2 * (size_t)Xm + scan;
   const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G + (Cm > kScanC ? 2 * C : 0);
   const size_t n16 = C + G;
   return ((8 * n64 + 4 * n32 + 2 * n16) + 15) & ~(size_t)15;
@@ -81,8 +82,9 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.bS = d; d += CX;
   t.q = d; d += CX;
   t.qa = d; d += CX;
-  t.hpn = d; d += CX;
-  t.hpq = d; d += CX;
+  t.car = d; d += CX;
+  t.hppn = d; d += C;
+  t.hppq = d; d += C;
   t.Ahat = d; d += CA;
   t.Amax = d; d += CA;
   t.qA = d; d += CA;
@@ -265,18 +267,26 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
   __syncthreads();
   // OS preemption by higher process-priority executors of the same core does
   // not depend on the chain order: per (chain, executor), the column totals
-  // over those executors minus the chain's own entries
+  // over those executors minus the chain's own entries, weighted by the
+  // chain's sub-chains on the executor (numerator) or counted once where it
+  // has any (utilisation)
   for (int c = threadIdx.x; c < C; c += kWave) {
+    int64_t nsum = 0, qsum = 0;
     for (int e = 0; e < X; ++e) {
+      const int i = c * X + e;
+      t.car[i] = t.Ece[i] + t.Acce[i] + t.epce[i];
+      const int64_t rce = t.runs[i];
       int64_t n = 0, q = 0;
       for (uint32_t m = (uint32_t)t.hpx[e]; m; m &= m - 1) {
         const int e2 = __ffs(m) - 1;
         n += 2 * (t.colw[e2] - hpp_w(t, c, e2, X));
         q += t.colw[X + e2] - hpp_q(t, c, e2, X);
       }
-      t.hpn[c * X + e] = n;
-      t.hpq[c * X + e] = q;
+      nsum += rce * n;
+      qsum += rce > 0 ? q : 0;
     }
+    t.hppn[c] = nsum;
+    t.hppq[c] = qsum;
   }
   __syncthreads();
 }
@@ -380,14 +390,8 @@ __device__ __forceinline__ void rm_inversions(const FeatTables &t, const int16_t
 }
 
 __device__ __forceinline__ void hpp_terms(const FeatTables &t, int c, int X, FeatNums &f) {
-  int64_t n = 0, q = 0;
-  for (int e = 0; e < X; ++e) {
-    const int64_t rce = t.runs[c * X + e];
-    n += rce * t.hpn[c * X + e];
-    q += rce > 0 ? t.hpq[c * X + e] : 0;
-  }
-  f.n_hpp = n;
-  f.q_hpp = q;
+  f.n_hpp = t.hppn[c];
+  f.q_hpp = t.hppq[c];
 }
 
 // ---- prefix-scan schedule (sets of more than kScanC chains)
@@ -521,7 +525,7 @@ __device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables
       const int i = c * X + e;
       vq = t.q[i];
       vqa = t.qa[i];
-      vcar = t.Ece[i] + t.Acce[i] + t.epce[i];
+      vcar = t.car[i];
       rce = t.runs[i];
       vbl = t.bl[i];
       vbs = t.bS[i];
@@ -628,7 +632,7 @@ __device__ void feat_candidate_scan(const DevBatch &b, int64_t set, const FeatTa
         const int i = c * X + e;
         vq = t.q[i];
         vqa = t.qa[i];
-        vcar = t.Ece[i] + t.Acce[i] + t.epce[i];
+        vcar = t.car[i];
         rce = t.runs[i];
       }
       const int64_t vh = rce > 0 ? 1 : 0;
