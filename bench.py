@@ -45,7 +45,7 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "482aa273ceed1ba64fc5fd698ecd8d217a12c9f4f065627f2562e09cd841c651",
+TRAFFIC = {"sha256": "a0e49d1e32e9782dcb0c96032919df60d99f46a00a7e69e92209885b4aacba1e",
            "bytes_per_launch": 15.16e9, "sets": 1_000_000, "waves_per_cu": 16}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 

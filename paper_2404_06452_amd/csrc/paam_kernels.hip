@@ -13,11 +13,12 @@
 //
 // Schedule.  One wavefront per chain set, pulled from a work queue in
 // decreasing estimated cost.  Lanes run over segments (Lemma 2), then over
-// sub-chains (Theorem 1).  All sub-chains of a set iterate together: every
-// sweep rebuilds the per-executor interference weights (hp and hpp terms of
-// Eq. 6) from the current H* values and re-evaluates, packed into full
-// 64-lane chunks, only the sub-chains that have not converged or whose
-// weights changed.  Each iterate starts below the least fixed point and the
+// sub-chains (Theorem 1).  All sub-chains of a set iterate together: the
+// per-executor interference weights (hp and hpp terms of Eq. 6) are built
+// once and then updated by every change of an H* value, and each sweep
+// re-evaluates, packed into full 64-lane chunks, only the sub-chains that
+// have not converged or read a weight that changed.  Each iterate starts
+// below the least fixed point and the
 // system is monotone, so this chaotic iteration ends at the same least fixed
 // point a sequential evaluation in dependency order reaches.
 #include <hip/hip_runtime.h>

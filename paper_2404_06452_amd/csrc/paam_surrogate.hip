@@ -17,12 +17,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ features
 
-// Two schedules compute identical features.  Sets of up to 64 chains: a wave
-// computes up to kMaxGroup consecutive candidates at once (lane g*C + c holds
-// chain c of candidate g), each lane summing over the other chains directly.
-// Larger sets: one candidate at a time; wave-wide prefix sums and suffix
-// maxima over the rank order give every chain's higher- and lower-priority
-// totals by lookup (O(C (X + NA)) per candidate instead of O(C^2 X)).
+// Both schedules take every chain's higher-priority totals from prefix sums
+// and its lower-priority terms from suffix maxima and counts over the rank
+// order (O(C (X + NA)) per candidate).  Sets of up to 64 chains: a wave takes
+// up to kMaxGroup consecutive candidates at once (lane g*C + r holds the chain
+// at rank r of candidate g) and scans within each candidate's lanes.  Larger
+// sets: one candidate at a time over 64-rank chunks with running totals.
 constexpr int kMaxGroup = 16;
 constexpr int kScanC = 64;  // sets with more chains use the prefix-scan schedule
 constexpr int kFwd = 9;     // numerators of a chain from the prefix-scan schedule's forward pass
@@ -31,7 +31,8 @@ constexpr int kFwd = 9;     // numerators of a chain from the prefix-scan schedu
 constexpr int kScanCarry = 7 * (kMaxExec + kMaxAccel);
 
 // Per-wave tables: a set's order-independent totals (built once per set), the
-// walk state, and the per-candidate ranks, bucket levels and scans.
+// walk state, the ranks and orders of a pass's candidates, and the forward
+// numerators and inversion counts of the large-set schedule.
 struct FeatTables {
   int64_t *Ec, *Acc, *epc, *Emax, *qsum, *qasum, *T, *D;  // [Cm]
   int64_t *Ece, *Acce, *epce, *bl, *bS, *q, *qa;          // [Cm][X]
