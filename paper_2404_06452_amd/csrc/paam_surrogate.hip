@@ -988,45 +988,81 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
       t0 = load_x8(X + (size_t)r * NF, 8 * lg, rv);
       t1 = load_x8(X + (size_t)r * NF, 32 + 8 * lg, rv);
     };
-    bf16x8 na0, na1;
-    load_tile(0, 0, na0, na1);
-    for (int m = 0; m < 16; ++m) {
-      const int mb = w * 16 + m;
-      const int rows = __shfl(myrows, m);
-      float pool[16];
-      for (int nt = 0; nt < 16; ++nt) pool[nt] = 0.0f;
-      for (int r0 = 0;; r0 += 16) {
-        const bf16x8 a0 = na0, a1 = na1;
-        if (r0 + 16 < rows) {
-          load_tile(m, r0 + 16, na0, na1);
-        } else if (m + 1 < 16) {
-          load_tile(m + 1, 0, na0, na1);
+    // every candidate of the wave within one 16-row tile (sets of up to 16
+    // chains): four candidates share each W1 fragment read from LDS, and a
+    // candidate's pooled sums come straight from its tile
+    if (!__any(l < 16 && myrows > 16)) {
+      for (int m0 = 0; m0 < 16; m0 += 4) {
+        bf16x8 a[4][2];
+        int rows[4];
+        for (int j = 0; j < 4; ++j) {
+          rows[j] = __shfl(myrows, m0 + j);
+          load_tile(m0 + j, 0, a[j][0], a[j][1]);
         }
-        if (r0 < rows) {
-          for (int nt = 0; nt < 16; ++nt) {
-            const int n = nt * 16 + li;
-            const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
-            const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
+        for (int nt = 0; nt < 16; ++nt) {
+          const int n = nt * 16 + li;
+          const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
+          const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
+          const float bias = bias1[nt];
+          for (int j = 0; j < 4; ++j) {
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][0], bb0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][1], bb1, acc, 0, 0, 0);
             float sacc = 0.0f;
-            for (int j = 0; j < 4; ++j) {
-              const int rr = r0 + 4 * lg + j;
-              const float z = acc[j] + bias1[nt];
-              sacc += (rr < rows && z > 0.0f) ? z : 0.0f;
+            for (int i = 0; i < 4; ++i) {
+              const int rr = 4 * lg + i;
+              const float z = acc[i] + bias;
+              sacc += (rr < rows[j] && z > 0.0f) ? z : 0.0f;
             }
-            pool[nt] += sacc;
+            float sv = 0.0f + sacc;
+            sv += __shfl_xor(sv, 16);
+            sv += __shfl_xor(sv, 32);
+            const float pv = rows[j] > 0 ? sv / (float)rows[j] : 0.0f;
+            if (lg == 0) Pq[(w * 16 + m0 + j) * kPqStride + nt * 16 + li] = bf16_rne(pv);
           }
         }
-        if (r0 + 16 >= rows) break;
       }
-      for (int nt = 0; nt < 16; ++nt) {
-        float sv = pool[nt];
-        sv += __shfl_xor(sv, 16);
-        sv += __shfl_xor(sv, 32);
-        const float p = rows > 0 ? sv / (float)rows : 0.0f;
-        if (lg == 0) Pq[mb * kPqStride + nt * 16 + li] = bf16_rne(p);
+    } else {
+      bf16x8 na0, na1;
+      load_tile(0, 0, na0, na1);
+      for (int m = 0; m < 16; ++m) {
+        const int mb = w * 16 + m;
+        const int rows = __shfl(myrows, m);
+        float pool[16];
+        for (int nt = 0; nt < 16; ++nt) pool[nt] = 0.0f;
+        for (int r0 = 0;; r0 += 16) {
+          const bf16x8 a0 = na0, a1 = na1;
+          if (r0 + 16 < rows) {
+            load_tile(m, r0 + 16, na0, na1);
+          } else if (m + 1 < 16) {
+            load_tile(m + 1, 0, na0, na1);
+          }
+          if (r0 < rows) {
+            for (int nt = 0; nt < 16; ++nt) {
+              const int n = nt * 16 + li;
+              const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
+              const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
+              f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
+              float sacc = 0.0f;
+              for (int j = 0; j < 4; ++j) {
+                const int rr = r0 + 4 * lg + j;
+                const float z = acc[j] + bias1[nt];
+                sacc += (rr < rows && z > 0.0f) ? z : 0.0f;
+              }
+              pool[nt] += sacc;
+            }
+          }
+          if (r0 + 16 >= rows) break;
+        }
+        for (int nt = 0; nt < 16; ++nt) {
+          float sv = pool[nt];
+          sv += __shfl_xor(sv, 16);
+          sv += __shfl_xor(sv, 32);
+          const float p = rows > 0 ? sv / (float)rows : 0.0f;
+          if (lg == 0) Pq[mb * kPqStride + nt * 16 + li] = bf16_rne(p);
+        }
       }
     }
     __syncthreads();

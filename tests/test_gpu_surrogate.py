@@ -169,8 +169,11 @@ def _network_batch(preset="sweep", n_sets=40, n=70, util=300, seed=7):
     return dev, pairs, f["feat"].shape[1], feat, count, x, ro
 
 
-def test_forward_within_tolerance():
-    dev, pairs, rs, feat, count, x, ro = _network_batch()
+@pytest.mark.parametrize("preset", ["sweep", "search"])
+def test_forward_within_tolerance(preset):
+    # search sets (16 chains) take the forward kernel's one-tile path, sweep
+    # sets (4-64 chains) mostly the multi-tile path
+    dev, pairs, rs, feat, count, x, ro = _network_batch(preset)
     n = len(pairs)
     for seed, b2 in ((1, 0.05), (2, 0.0)):
         theta = chaingen.mlp_init(seed)
