@@ -44,6 +44,7 @@ struct FeatTables {
   int64_t *fwd;                                            // [Cm][kFwd] forward-pass numerators by rank
   int32_t *inv;                                            // [2][Cm] RM inversions above / below
   int32_t *S, *dl, *ncb, *mine, *uses, *spin;              // [Cm]
+  uint32_t *tmpl;                                          // [Cm][13] order-independent feature words
   int32_t *runs;                                           // [Cm][X]
   int32_t *dca, *nra;                                      // [Cm][NA]
   int32_t *hpx;                                            // [Xm]
@@ -58,7 +59,7 @@ __host__ __device__ inline size_t feat_table_bytes(int Cm, int Xm, int NAm) {
   const size_t G = Cm > 64 ? (size_t)Cm : 64;
   const size_t scan = Cm > kScanC ? (size_t)kFwd * C : 0;
   const size_t n64 = 10 * C + 8 * CX + 3 * CA + 8 + 2 * (size_t)Xm + scan;
-  const size_t n32 = 6 * C + CX + 2 * CA + Xm + C + 64 + G + (Cm > kScanC ? 2 * C : 0);
+  const size_t n32 = 6 * C + 13 * C + CX + 2 * CA + Xm + C + 64 + G + (Cm > kScanC ? 2 * C : 0);
   const size_t n16 = C + G;
   return ((8 * n64 + 4 * n32 + 2 * n16) + 15) & ~(size_t)15;
 }
@@ -103,6 +104,7 @@ __device__ FeatTables carve_feat(unsigned char *base, int Cm, int Xm, int NAm) {
   t.mine = i; i += C;
   t.uses = i; i += C;
   t.spin = i; i += C;
+  t.tmpl = reinterpret_cast<uint32_t *>(i); i += 13 * C;
   t.runs = i; i += CX;
   t.dca = i; i += CA;
   t.nra = i; i += CA;
@@ -304,11 +306,13 @@ struct FeatNums {
   double f35;
 };
 
-// The 48 features of chain c of rank rho, written to row[0..47].  Feature k
-// here is feature k of the documented list; each is (double)N / (double)M of
-// exact integers.
-__device__ void feat_write(const DevBatch &b, int64_t set, const FeatTables &t, int c, int rho,
-                           const FeatNums &f, uint16_t *row) {
+// Words of a row (two bfloat16 each) that hold only order-independent
+// features: 0-13 (words 0-6), 14 (low half of word 7), 38-43 (words 19-21),
+// 44 (low half of word 22) and 47 (high half of word 23).  Built once per
+// set into t.tmpl[c][13] = words 0-7 and 19-23.
+constexpr int kTmplWords = 13;
+
+__device__ void feat_template(const DevBatch &b, int64_t set, const FeatTables &t, int c) {
   const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
   const int X = (int)(b.set_exec_off[set + 1] - b.set_exec_off[set]);
   const int NA = (int)(b.set_accel_off[set + 1] - b.set_accel_off[set]);
@@ -334,6 +338,40 @@ __device__ void feat_write(const DevBatch &b, int64_t set, const FeatTables &t, 
   put_feat(w, 12, t.spin[c] ? 1.0 : 0.0);
   put_feat(w, 13, fratio(t.qsum[c], kQ));
   put_feat(w, 14, fratio(t.qasum[c], kQ));
+  put_feat(w, 38, fratio(t.setv[0], (int64_t)X * kQ));
+  put_feat(w, 39, fratio(t.setv[4], kQ));
+  put_feat(w, 40, fratio(t.setv[1], kQ));
+  put_feat(w, 41, fratio(C, 256));
+  put_feat(w, 42, fratio(X, 8));
+  put_feat(w, 43, fratio(NA, 8));
+  put_feat(w, 44, fratio(t.setv[3], T));
+  put_feat(w, 47, fratio(t.Ec[c] + t.Acc[c], t.setv[2]));
+  uint32_t *o = t.tmpl + (size_t)c * kTmplWords;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o[i] = w[i];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) o[8 + i] = w[19 + i];
+}
+
+// The 48 features of chain c of rank rho, written to row[0..47]: the
+// order-independent words from t.tmpl, the others from the numerators.
+// Feature k here is feature k of the documented list; each is
+// (double)N / (double)M of exact integers.
+__device__ void feat_write(const DevBatch &b, int64_t set, const FeatTables &t, int c, int rho,
+                           const FeatNums &f, uint16_t *row) {
+  const int C = (int)(b.set_chain_off[set + 1] - b.set_chain_off[set]);
+  const int64_t hop = b.eps_hop[set];
+  const int64_t D = t.D[c];
+  const int S = t.S[c];
+  const int64_t own = t.Ec[c] + t.Acc[c] + t.epc[c] + (int64_t)(S - 1) * hop;
+  uint32_t w[24];
+  const uint32_t *tw = t.tmpl + (size_t)c * kTmplWords;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) w[i] = tw[i];
+#pragma unroll
+  for (int i = 8; i < 19; ++i) w[i] = 0u;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) w[19 + i] = tw[8 + i];
   put_feat(w, 15, fratio(rho, C));
   put_feat(w, 16, fratio(C - 1 - rho, C));
   put_feat(w, 17, rho == 0 ? 1.0 : 0.0);
@@ -357,18 +395,10 @@ __device__ void feat_write(const DevBatch &b, int64_t set, const FeatTables &t, 
   put_feat(w, 35, f.f35);
   put_feat(w, 36, fratio(f.n36, C));
   put_feat(w, 37, f.f37 ? 1.0 : 0.0);
-  put_feat(w, 38, fratio(t.setv[0], (int64_t)X * kQ));
-  put_feat(w, 39, fratio(t.setv[4], kQ));
-  put_feat(w, 40, fratio(t.setv[1], kQ));
-  put_feat(w, 41, fratio(C, 256));
-  put_feat(w, 42, fratio(X, 8));
-  put_feat(w, 43, fratio(NA, 8));
-  put_feat(w, 44, fratio(t.setv[3], T));
   const int64_t n_est = own + f.n_carry + f.n_bs + f.n_hpp + f.n_acc + f.n_bacc;
   const int64_t q_est = f.q21 + f.q22 + f.q_hpp + f.q33;
   put_feat(w, 45, fratio(n_est, D));
   put_feat(w, 46, fratio(n_est, D) + fratio(q_est, kQ));
-  put_feat(w, 47, fratio(t.Ec[c] + t.Acc[c], t.setv[2]));
   // the row (96 bytes, 16-byte aligned) in six 16-byte stores
   uint4 *dst = reinterpret_cast<uint4 *>(row);
 #pragma unroll
@@ -858,6 +888,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
       for (int64_t k = lane; k < n_k; k += kWave) L.count[out0 + k] = -2;
       continue;
     }
+    for (int c = lane; c < C; c += kWave) feat_template(L.b, set, t, c);
     for (int c = lane; c < C; c += kWave) {
       const int r = L.b.rank0[c0 + c];
       t.order[r] = c;
