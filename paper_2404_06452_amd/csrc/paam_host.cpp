@@ -791,11 +791,11 @@ static int grid_items(int64_t n_items, int waves_per_cu) {
   return (int)std::max<int64_t>(g, 1);
 }
 
-// Features grid: as many waves per CU as the kernel's registers allow (16:
-// it is built for four waves per SIMD), fewer when its LDS tables do not fit
-// that many.
+// Features grid: as many waves per CU as the kernel's registers allow (the
+// LDS-table kernel is built for four waves per SIMD, the global-table kernel
+// for three), fewer when the LDS tables do not fit that many.
 static int feat_grid(const paam_chainset *cs, int64_t n_items) {
-  int w = 16;
+  int w = 12;
   if (paam::feat_in_lds(cs->dev)) {
     const size_t per = paam::feat_wave_bytes(cs->dev);
     w = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(per, 1));

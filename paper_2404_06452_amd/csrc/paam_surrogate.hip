@@ -846,7 +846,7 @@ __device__ void feat_candidate_scan(const DevBatch &b, int64_t set, const FeatTa
 // up to 64 consecutive candidates of one set.  Tables in LDS (kLds) or in the
 // wave's global scratch.
 template <bool kLds>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void features_kernel(FeatLaunch L) {
+__device__ __forceinline__ void features_body(FeatLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char *base = kLds ? lds_raw : L.scratch + (size_t)blockIdx.x * L.scratch_stride;
   const int NAmx = L.b.max_NA > 0 ? L.b.max_NA : 1;
@@ -932,6 +932,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
       __syncthreads();
     }
   }
+}
+
+// LDS tables (sets of up to 64 chains): four waves per SIMD.  Global tables:
+// the register budget of three waves per SIMD, without spills.
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void features_kernel_lds(
+    FeatLaunch L) {
+  features_body<true>(L);
+}
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void features_kernel_glb(
+    FeatLaunch L) {
+  features_body<false>(L);
 }
 
 // ------------------------------------------------------------------ network
@@ -1286,10 +1297,10 @@ int launch_features(const FeatLaunch &L, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (L.n_items == 0) return 0;
   if (feat_in_lds(L.b)) {
-    hipLaunchKernelGGL(features_kernel<true>, dim3(L.grid), dim3(kWave), feat_wave_bytes(L.b), st,
+    hipLaunchKernelGGL(features_kernel_lds, dim3(L.grid), dim3(kWave), feat_wave_bytes(L.b), st,
                        L);
   } else {
-    hipLaunchKernelGGL(features_kernel<false>, dim3(L.grid), dim3(kWave), 0, st, L);
+    hipLaunchKernelGGL(features_kernel_glb, dim3(L.grid), dim3(kWave), 0, st, L);
   }
   return (int)hipGetLastError();
 }
