@@ -62,3 +62,45 @@ def test_search_matches_oracle_mixed_size_classes(paam):
                                           n_buckets=3, util=(0.002, 0.02), seed=95)
     g = check(paam, chaingen.generate(p, 24), 12, 31)
     print("found", (g["found"] >= 0).mean(), flush=True)
+
+
+def test_full_size_search_workload_sampled(paam):
+    # the search workload at its full size (100,000 sets x 256 candidates, the
+    # launch the bench times), compared with the oracle on the first sets:
+    # plain search at 5 % of the utilisation, and guided search (top 16 with
+    # fallback) driven by seeded synthetic scores the oracle also receives
+    import torch
+    cs = chaingen.generate("search", 100_000)
+    dev = paam.Chainset(cs)
+    n_cand, seed, util = 256, 2404, 50
+    g = paam.search(dev, n_cand, seed, util_permille=util)
+    m = 600
+    r = oracle.search(cs, n_cand, seed, util_permille=util, sets=(0, m), threads=8)
+    assert np.array_equal(g["found"][:m], r["found"][:m])
+    assert np.array_equal(g["n_exact"][:m], r["n_eval"][:m])
+    assert 0.2 < (g["found"] >= 0).mean() < 0.5
+    sc = chaingen.random_scores(cs.n_sets * n_cand, 17)
+    g = paam.search(dev, n_cand, seed, scores=torch.from_numpy(sc).cuda(), guided=True,
+                    top_k=16, fallback=True, util_permille=util)
+    m = 200
+    r = oracle.guided_search(cs, n_cand, seed, sc, 16, fallback=True, util_permille=util,
+                             sets=(0, m))
+    assert np.array_equal(g["found"][:m], r["found"][:m])
+    assert np.array_equal(g["n_exact"][:m], r["n_eval"][:m])
+
+
+def test_large_set_workload_sampled(paam):
+    # 256-chain sets in the size the bench launches them (10,000), verdicts of
+    # the uploaded order and every chain bound at a low utilisation compared
+    # with the oracle on the first sets
+    cs = chaingen.generate("large", 10_000)
+    dev = paam.Chainset(cs)
+    m = 24
+    g = paam.wcrt(dev, full=False)
+    r = oracle.wcrt(cs, full=False, sets=(0, m), threads=8)
+    assert np.array_equal(g["sched"][:m], r["sched"][:m])
+    g = paam.wcrt(dev, full=True, util_permille=5)
+    r = oracle.wcrt(cs, full=True, util_permille=5, sets=(0, m), threads=8)
+    n_ch = int(cs.set_chain_off[m])
+    assert np.array_equal(g["chain_R"][:n_ch], r["chain_R"][:n_ch])
+    assert np.array_equal(g["worst_R"][:m], r["worst_R"][:m])
