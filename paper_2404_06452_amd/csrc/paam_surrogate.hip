@@ -913,13 +913,31 @@ __device__ __forceinline__ void features_body(FeatLaunch L) {
     G = G < kMaxGroup ? G : kMaxGroup;
     for (int64_t kb = k0; kb < k0 + n_k; kb += G) {
       const int ng = (int)(k0 + n_k - kb < G ? k0 + n_k - kb : G);
-      // ranks of the group's candidates
-      for (int j = 0; j < ng; ++j) {
-        walk_order(t.order, t.rank, C, L.seed, set, cur, kb + j, t.buf);
-        cur = kb + j;
-        for (int c = lane; c < C; c += kWave) t.rankg[j * C + c] = t.rank[c];
-        __syncthreads();
+      // ranks of the pass's candidates: the walk to candidate kb, then one
+      // swap per further candidate, applied by each lane to its own chain's
+      // rank (the chains at the two swapped ranks trade ranks)
+      walk_order(t.order, t.rank, C, L.seed, set, cur, kb, t.buf);
+      if (C >= 2 && lane >= 1 && lane < ng) t.buf[lane] = swap_positions(L.seed, set, kb + lane, C);
+      __syncthreads();
+      for (int c = lane; c < C; c += kWave) {
+        int r = t.rank[c];
+        t.rankg[c] = (int16_t)r;
+        for (int j = 1; j < ng; ++j) {
+          if (C >= 2) {
+            const int32_t pq = t.buf[j];
+            const int pa = pq & 0xffff, pb = pq >> 16;
+            r = r == pa ? pb : (r == pb ? pa : r);
+          }
+          t.rankg[j * C + c] = (int16_t)r;
+        }
       }
+      __syncthreads();
+      for (int c = lane; c < C; c += kWave) {
+        const int r = t.rankg[(ng - 1) * C + c];
+        t.rank[c] = (int16_t)r;
+        t.order[r] = c;
+      }
+      cur = kb + ng - 1;
       // chain at each rank of every candidate of the pass
       for (int idx = lane; idx < ng * C; idx += kWave) {
         const int g = idx / C, c = idx - g * C;
