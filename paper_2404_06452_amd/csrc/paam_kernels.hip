@@ -634,8 +634,19 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
         S.r[s] = rn;
         if (needL3) S.hs[s] = hsn;
       }
+      if (!full) {
+        // verdict mode: a chain of this chunk whose partial end-to-end sum
+        // (a lower bound) already exceeds its deadline proves the miss
+        bool miss = false;
+        if (valid) miss = L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho];
+        if (wave_any(miss)) {
+          missed = true;
+          break;
+        }
+      }
     }
     __syncthreads();
+    if (missed) break;
     if (!full) {
       // every iterate is a lower bound: a partial end-to-end sum above the
       // deadline proves the miss
