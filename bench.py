@@ -45,8 +45,8 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "a0e49d1e32e9782dcb0c96032919df60d99f46a00a7e69e92209885b4aacba1e",
-           "bytes_per_launch": 15.16e9, "sets": 1_000_000, "waves_per_cu": 16}
+TRAFFIC = {"sha256": "5b3b3a689502462f177fa134f38d102b5c3d88da51d78cb382079aa9ff227827",
+           "bytes_per_launch": 15.14e9, "sets": 1_000_000, "waves_per_cu": 16}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
