@@ -344,7 +344,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the analysis shards across GPUs by set range with no "
-              "exchange, but this build runs and reports a single MI355X only (--gpus 1).",
+              "exchange, but this benchmark runs and reports a single MI355X only (--gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 
