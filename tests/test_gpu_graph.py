@@ -109,3 +109,61 @@ def test_graph_replays_match_eager_and_oracle():
         assert np.array_equal(got[2][2][found_chain], eager[2][2][found_chain]), rep
         assert (got[2][2][~found_chain] == -7).all(), rep
     del graph
+
+
+def test_graph_replays_of_scoring_and_guided_search():
+    """Features, network forward and the guided confirmation of the top 8,
+    captured together: every replay reproduces the eager scores, finds and
+    evaluation counts bit for bit.  (The oracle parity of each step, on
+    seeded scores for the search, is covered by the surrogate and search
+    tests.)"""
+    import torch
+
+    from paper_2404_06452_amd import _paam
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    note("graph: scoring + guided top-8, search 400 sets x 128")
+    n_cand, seed, top_k, util = 128, 9, 8, 50
+    ss = chaingen.generate("search", 400, set_begin=9100)
+    sdev = _paam.Chainset(ss)
+    net = _paam.Network(chaingen.mlp_init(3), device="cuda:0")
+    scores = torch.empty(ss.n_sets * n_cand, dtype=torch.float32, device="cuda:0")
+    so = _paam.search_opts(n_cand, seed, util_permille=util)
+    go = _paam.search_opts(n_cand, seed, guided=True, top_k=top_k, fallback=False, scores=scores,
+                           util_permille=util)
+    sout = _paam.SearchOut(sdev, with_prio=False)
+    sws = _paam.workspace(_paam.paam_score_bytes(sdev, so))
+    gws = _paam.workspace(_paam.paam_search_bytes(sdev, go))
+    stream = torch.cuda.Stream()
+
+    def step(s):
+        _paam.paam_score_candidates(sdev, so, net.params, net.packed, scores, sws, s)
+        _paam.paam_priority_search(sdev, go, sout, gws, s)
+
+    def snapshot():
+        torch.cuda.synchronize()
+        return (scores.cpu().numpy().copy(), sout.found.cpu().numpy(), sout.n_exact.cpu().numpy())
+
+    with torch.cuda.stream(stream):
+        step(stream)
+    eager = snapshot()
+    assert np.isfinite(eager[0]).all()
+    assert (eager[1] >= 0).any(), "the guided search should admit some sets"
+    assert ((eager[2] >= 1) & (eager[2] <= top_k)).all()
+
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        step(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    x = torch.randn(256, 256, device="cuda:0")
+    for rep in range(3):
+        note("graph: scoring replay %d" % rep)
+        x = torch.relu(x @ x.T / 256.0)
+        scores.fill_(float("nan"))
+        sout.found.fill_(-7)
+        sout.n_exact.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        got = snapshot()
+        for u, v in zip(eager, got):
+            assert np.array_equal(u, v), "scoring replay %d differs from the eager outputs" % rep
+    del graph
