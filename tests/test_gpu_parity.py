@@ -153,10 +153,12 @@ def test_empty_and_degenerate_batches(paam):
 def test_repeatable_and_schedule_independent(paam):
     """Identical results across launches and persistent-grid sizes (a data
     race or an order-dependent iteration would show up here)."""
-    cs = chaingen.generate("sweep", 3000, set_begin=5000)
+    # 20,000 sets: the class of 33-64 chains holds more than 8,192, so at 32
+    # waves per CU its grid is twice what its LDS lets the CUs hold at once
+    cs = chaingen.generate("sweep", 20000, set_begin=5000)
     dev = paam.Chainset(cs)
     ref = paam.wcrt(dev, full=True, util_permille=400)
-    for w in (1, 2, 4, 16):
+    for w in (1, 2, 4, 16, 32):
         g = paam.wcrt(dev, full=True, util_permille=400, waves_per_cu=w)
         for k in ref:
             assert np.array_equal(ref[k], g[k]), (w, k)
