@@ -98,3 +98,20 @@ def test_product_and_oracle_share_no_code():
         text = open(path).read()
         assert "paper_2404_06452_amd" not in text and "paam.h" not in text, path
         assert "paam_internal" not in text, path
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """With libpaam.so absent the binding raises at its first call: there is
+    no fallback path to run instead of the HIP library."""
+    from paper_2404_06452_amd import _paam, chaingen
+    saved = (_paam._lib, _paam.LIBPAAM)
+    try:
+        _paam._lib = None
+        _paam.LIBPAAM = str(tmp_path / "libpaam.so")
+        with pytest.raises(_paam.PaamError, match="not built"):
+            _paam.lib()
+        # the upload of a batch is the first library call of the product path
+        with pytest.raises(_paam.PaamError, match="not built"):
+            _paam.Chainset(chaingen.generate("small", 2), device="cpu")
+    finally:
+        _paam._lib, _paam.LIBPAAM = saved
