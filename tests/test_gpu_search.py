@@ -48,6 +48,19 @@ def test_search_matches_oracle_search_preset(paam):
     check(paam, chaingen.generate("search", 500), 256, 777)
 
 
+def test_search_independent_of_the_persistent_grid(paam):
+    # 5,000 sets: at 32 waves per CU the grid is larger than the number of
+    # search waves the CUs hold at once, at 1 it is 256 waves
+    cs = chaingen.generate("search", 5000, set_begin=60000)
+    ref = check(paam, cs, 32, 555, util_permille=50)
+    assert (ref["found"] >= 0).any()
+    dev = paam.Chainset(cs)
+    for w in (1, 4, 32):
+        g = paam.search(dev, 32, 555, util_permille=50, waves_per_cu=w)
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (w, k)
+
+
 def test_search_matches_oracle_varied_sets(paam):
     p = chaingen.PRESETS["small"].replace(seed=93, chains=(1, 10), cbs=(1, 4), n_exec=3,
                                           util=(0.02, 0.3), T=(20.0, 4000.0), n_buckets=2,
