@@ -118,6 +118,19 @@ def test_candidate_wcrt_exact(preset, n_sets, n_pairs, cap):
     assert bad["sched"][0] == -2
 
 
+def test_candidate_wcrt_independent_of_the_persistent_grid():
+    # 6,000 pairs: at 32 waves per CU the grid holds more waves than the CUs
+    # run at once; every grid gives the oracle's targets
+    cs = chaingen.generate("sweep", 400, set_begin=31000)
+    dev = _paam.Chainset(cs, device=DEV)
+    pairs = _pairs(cs, 6000, 5, utils=(1000, 400, 60))
+    r = oracle.candidate_analysis(cs, pairs, SEED, cap_mult=2)
+    for w in (1, 4, 32):
+        g = _paam.candidates(dev, pairs, SEED, cap_mult=2, waves_per_cu=w)
+        for k in ("sched", "worst_R", "worst_D", "ratio"):
+            assert np.array_equal(g[k], r[k]), (w, k)
+
+
 @pytest.mark.parametrize("preset,n_sets,n_cand,top_k,fallback,util,ties", [
     ("small", 60, 64, 8, True, 100, False),
     ("small", 60, 64, 8, False, 100, True),
