@@ -290,3 +290,40 @@ def test_training_lowers_loss():
     assert np.array_equal(tg.ratio[:40].cpu().numpy(), r["ratio"])
     losses = tr.fit(pairs, tg.ratio, epochs=4, lr=2e-3, order_seed=1)
     assert losses[-1] < 0.5 * losses[0], losses
+
+
+def test_trained_network_gains_over_the_search_without_it():
+    """What the learned ranking adds: trained on sweep-generator sets it
+    ranks the candidate orders of unseen search sets so that confirming only
+    its top 16 finds more schedulable sets than an untrained network's top 16
+    or the first 16 candidates in index order, and nearly every set plain
+    search over all 256 candidates finds."""
+    from paper_2404_06452_amd import surrogate
+    n_cand, top_k, seed, util = 256, 16, 2404, 50
+    tcs = chaingen.generate("sweep", 20000)
+    tdev = _paam.Chainset(tcs, device=DEV)
+    net = _paam.Network(chaingen.mlp_init(seed), device=DEV)
+    tr = Trainer(tdev, net, seed, batch=4096)
+    pairs = torch.from_numpy(surrogate.recipe_pairs(tcs.n_sets, 2_000_000, seed)).to(DEV)
+    target = tr.targets(pairs).ratio[:2_000_000]
+    tr.fit(pairs, target, epochs=2, lr=2e-3, lr_final=1e-4, order_seed=seed)
+    untrained = _paam.Network(chaingen.mlp_init(seed + 7), device=DEV)
+
+    cs = chaingen.generate("search", 5000, set_begin=70000)
+    dev = _paam.Chainset(cs, device=DEV)
+    plain = _paam.search(dev, n_cand, seed, util_permille=util)["found"] >= 0
+    first = _paam.search(dev, top_k, seed, util_permille=util)["found"] >= 0
+
+    def guided(nw):
+        sc = _paam.score(dev, nw, n_cand, seed, util_permille=util)
+        g = _paam.search(dev, n_cand, seed, scores=sc, guided=True, top_k=top_k, fallback=False,
+                         util_permille=util)
+        assert (g["n_exact"] <= top_k).all()
+        return g["found"] >= 0
+
+    trained, untr = guided(net), guided(untrained)
+    print("found: plain %d, first %d in index order %d, untrained top %d %d, trained top %d %d" % (
+        plain.sum(), top_k, first.sum(), top_k, untr.sum(), top_k, trained.sum()), flush=True)
+    assert not (trained & ~plain).any()  # a guided find is a plain find
+    assert trained.sum() > untr.sum() and trained.sum() > first.sum()
+    assert trained.sum() >= 0.95 * plain.sum()
