@@ -188,6 +188,16 @@ def search_section(args, torch, log):
             entry["untrained_network_top_k_only"] = {"found_frac": float((f_un >= 0).mean()),
                                                      "found_vs_plain": rel(f_un),
                                                      "mean_exact_evals": float(e_un.mean())}
+            # the same budget without a ranking: the first top_k candidates of
+            # the walk, which starts at the uploaded rate-monotonic order
+            o_ix = _paam.search_opts(top_k, seed, util_permille=util)
+            ws_ix = _paam.workspace(_paam.paam_search_bytes(dev, o_ix))
+            t_ix = timed(lambda: _paam.paam_priority_search(dev, o_ix, out, ws_ix, stream))
+            f_ix, e_ix = out.found.cpu().numpy(), out.n_exact.cpu().numpy()
+            entry["first_k_in_index_order"] = {"sets_per_s": n / t_ix,
+                                               "found_frac": float((f_ix >= 0).mean()),
+                                               "found_vs_plain": rel(f_ix),
+                                               "mean_exact_evals": float(e_ix.mean())}
         res[name] = entry
         log("search %s: plain %.3g sets/s found %.3f evals %.1f | guided+fb %.3g sets/s found %.3f "
             "evals %.1f | top-%d %.3g sets/s found %.3f" % (
