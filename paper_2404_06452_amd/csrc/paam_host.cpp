@@ -69,7 +69,7 @@ struct Plan {
   std::vector<int32_t> run_cb_lo, run_cb_hi, chain_nrun, seg_order;
   std::vector<int16_t> rank0, seg_chain;
   std::vector<uint32_t> hpx_mask;
-  std::vector<double> Kd, rcp;
+  std::vector<double> Kd, rcp, KRr;
   std::vector<int32_t> buckets;
   std::vector<int64_t> work_order;
   int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0;
@@ -199,6 +199,8 @@ void fill_set(const paam_chainset_host *h, int64_t s, Plan &P) {
   for (int r = 0; r < C; ++r) {
     const int c = order[r];
     P.rank0[c0 + c] = (int16_t)r;
+    P.KRr[2 * (c0 + r)] = P.Kd[c0 + c];
+    P.KRr[2 * (c0 + r) + 1] = P.rcp[c0 + c];
   }
   // sub-chains in chain order, then sorted by (hpp above, rank, position)
   struct Run {
@@ -329,6 +331,7 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     P.Kd[c] = (double)(2 * h->T[c] - 1);
     P.rcp[c] = rcp_up(h->T[c]);
   }
+  P.KRr.resize(2 * NC);
   P.rank0.resize(NC);
   P.chain_nrun.assign(NC, 0);
   P.seg_chain.resize(NG);
@@ -389,7 +392,7 @@ struct Arena {
 
 struct Offsets {
   size_t set_chain_off, set_cb_off, set_seg_off, set_run_off, set_exec_off, set_accel_off, eps_hop,
-      work_order, T, D, Kd, rcp, rank0, chain_nrun, spin, E, cb_seg_off, A, seg_accel,
+      work_order, T, D, Kd, rcp, KRr, rank0, chain_nrun, spin, E, cb_seg_off, A, seg_accel,
       seg_chain, seg_order, run_chain, run_exec, run_cb_lo, run_cb_hi, hpx_mask, buckets, aeps,
       akappa, total;
 };
@@ -410,6 +413,7 @@ Offsets layout(const Plan &P) {
   o.D = a.take<int64_t>(P.n_chains);
   o.Kd = a.take<double>(P.n_chains);
   o.rcp = a.take<double>(P.n_chains);
+  o.KRr = a.take<double>(2 * P.n_chains);
   o.rank0 = a.take<int16_t>(P.n_chains);
   o.chain_nrun = a.take<int32_t>(P.n_chains);
   o.spin = a.take<uint8_t>(P.n_chains);
@@ -490,6 +494,7 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   put(buf, o.D, h->D, P.n_chains);
   put(buf, o.Kd, P.Kd.data(), P.n_chains);
   put(buf, o.rcp, P.rcp.data(), P.n_chains);
+  put(buf, o.KRr, P.KRr.data(), 2 * P.n_chains);
   put(buf, o.rank0, P.rank0.data(), P.n_chains);
   put(buf, o.chain_nrun, P.chain_nrun.data(), P.n_chains);
   put(buf, o.spin, h->spin, P.n_chains);
@@ -536,6 +541,7 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   BIND(D, int64_t);
   BIND(Kd, double);
   BIND(rcp, double);
+  BIND(KRr, double);
   BIND(rank0, int16_t);
   BIND(chain_nrun, int32_t);
   BIND(spin, uint8_t);

@@ -39,6 +39,8 @@ struct DevBatch {
   const int64_t *T, *D;        // [n_chains]
   const double *Kd;            // [n_chains] 2T - 1
   const double *rcp;           // [n_chains] 1/T rounded towards +inf
+  const double *KRr;           // [2 n_chains] per set, by rank under the uploaded priorities:
+                               // (2T - 1, 1/T rounded up) of the chain at that rank
   const int16_t *rank0;        // [n_chains] rank under the uploaded priorities, 0 = highest
   const int32_t *chain_nrun;   // [n_chains] sub-chains of the chain
   const uint8_t *spin;         // [n_chains]

@@ -77,12 +77,18 @@ struct Lds {
   double *WP, *Pt;                   // [X][C] hp+hpp weight (rank above), hpp weight (below)
   double *SB;                        // [X][C] blocking candidates, then staging of the first build
                                      // (in the wave's global scratch for large tables)
+  double *aek;                       // [NA][2] epsilon, kappa of each accelerator
   int32_t *rank;                     // [C] rank of a chain
   int32_t *nrs;                      // [C] sub-chains of the chain at a rank | busy-waits << 16
   int32_t *level;                    // [NA][C] bucket level of a user, -1 for a non-user
   int32_t *wmin, *pmax;              // [2][X] lowest rank whose WP changed, highest whose Pt
                                      // changed: as seen by this sweep, as recorded for the next
   int32_t *lpx;                      // [X] executors of the core with lower process priority
+  int32_t *hpx;                      // [X] executors of the core with higher process priority
+  int32_t *dmin, *dspin;             // [X] per step: lowest rank of a pending Lemma 3 sub-chain
+                                     // on the executor, pending busy-waiting ones on it
+  int32_t *dfirst, *dblk;            // [X] lowest rank of any Lemma 3 sub-chain on the executor;
+                                     // a higher-priority executor of its core holds a busy-waiting one
   int32_t *misc;                     // [16]
 };
 
@@ -91,6 +97,8 @@ struct Scratch {
   double *segAs, *segH;                    // [max_segs]
   double *r, *hs, *cst, *L2, *A0, *eps;    // [max_runs]
   int32_t *info, *alist;                   // [max_runs] packed sub-chain word, active list
+  double2 *qs;                             // [max_segs] Lemma 2 queue: (A*, g | packed rank, acc)
+  double2 *qr;                             // [max_runs] Theorem 1 queue: (constant, s | packed word)
 };
 
 __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
@@ -108,6 +116,8 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
     l.SB = d;
     d += Xm * Cm;
   }
+  l.aek = d;
+  d += 2 * NAm;
   int32_t *i = reinterpret_cast<int32_t *>(d);
   l.rank = i; i += Cm;
   l.nrs = i; i += Cm;
@@ -115,6 +125,11 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   l.wmin = i; i += 2 * Xm;
   l.pmax = i; i += 2 * Xm;
   l.lpx = i; i += Xm;
+  l.hpx = i; i += Xm;
+  l.dmin = i; i += Xm;
+  l.dspin = i; i += Xm;
+  l.dfirst = i; i += Xm;
+  l.dblk = i; i += Xm;
   l.misc = i;
   return l;
 }
@@ -135,6 +150,9 @@ __device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs
   s.L2 = d; d += max_runs;
   s.A0 = d; d += max_runs;
   s.eps = d; d += max_runs;
+  d = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(d) + 15) & ~(uintptr_t)15);
+  s.qs = reinterpret_cast<double2 *>(d); d += 2 * (size_t)max_segs;
+  s.qr = reinterpret_cast<double2 *>(d); d += 2 * (size_t)max_runs;
   int32_t *i = reinterpret_cast<int32_t *>(d);
   s.info = i; i += max_runs;
   s.alist = i;
@@ -145,6 +163,10 @@ __device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs
 // stops; the guard only makes termination unconditional.  A set that trips it
 // reports set_sched = -1.
 constexpr int kMaxIter = 1 << 20;
+
+// Evaluations of each lane's recurrence per engine step of the queue-driven
+// analysis: the refill and dependency bookkeeping of a step is shared by them.
+constexpr int kMicro = 2;
 
 // Packed word of a sub-chain: rank of its chain in bits 0-11 (fewer than
 // 4,096 chains per set), executor in bits 12-16, accelerator mask in bits
@@ -700,21 +722,759 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   __syncthreads();
 }
 
+// ------------------------- queue-driven analysis ---------------------------
+//
+// Source of the (2T - 1, 1/T rounded up) pair of the chain at rank h.  Under
+// the uploaded priorities it is the rank-ordered table built at upload, which
+// no kernel writes: a read at a wave-uniform rank is a scalar load, so the
+// inner loops read only the per-lane weights from LDS.  Under a candidate
+// order it is the wave's LDS table.
+struct KRConst {
+  static constexpr bool kUploaded = true;
+  const __attribute__((address_space(4))) double *p;  // (2T - 1, 1/T) pairs by rank
+  __device__ __forceinline__ double2 operator()(int h) const {
+    return make_double2(p[2 * h], p[2 * h + 1]);
+  }
+};
+struct KRShared {
+  static constexpr bool kUploaded = false;
+  const double2 *p;
+  __device__ __forceinline__ double2 operator()(int h) const { return p[h]; }
+};
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long lanes_below() {
+  return (1ull << threadIdx.x) - 1ull;
+}
+
+// Wave-wide integer max / min (DPP, no LDS traffic); every lane gets the result.
+extern "C" __device__ int __ockl_wfred_max_i32(int);
+extern "C" __device__ int __ockl_wfred_min_i32(int);
+__device__ __forceinline__ int wave_umax(int v) { return uniform_int(__ockl_wfred_max_i32(v)); }
+__device__ __forceinline__ int wave_umin(int v) { return uniform_int(__ockl_wfred_min_i32(v)); }
+
+// The analysis runs in one-wave workgroups, whose LDS operations take effect
+// in program order: within an engine step a compiler fence at wavefront scope
+// orders them, without the drain of outstanding global loads and stores that
+// a workgroup barrier implies.  Phase boundaries that hand data over through
+// global scratch keep the workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Inclusive suffix maximum over the lanes of a wave (lane i: max of lanes >= i).
+__device__ __forceinline__ unsigned long long wave_suffix_max_u64(unsigned long long v) {
+  for (int d = 1; d < kWave; d <<= 1) {
+    const unsigned long long w = __shfl_down(v, d);
+    if (threadIdx.x + d < kWave && w > v) v = w;
+  }
+  return v;
+}
+
+// Keys of the same-bucket blocking scan: (kLevTop - level) above the A* bits.
+// A* < 2^47 (times below 2^36 scaled by at most 1000, plus 2 kappa) and
+// levels below 2^15 (buckets are int16).
+constexpr int kKeyShift = 47;
+constexpr int kLevTop = 1 << 15;
+constexpr unsigned long long kKeyMask = (1ull << kKeyShift) - 1ull;
+
+// Two 32-bit fields in the bits of a double (queue records).
+__device__ __forceinline__ double pack2(int hi, int lo) { return __hiloint2double(hi, lo); }
+
+// Analyses one set under the uploaded priorities (kr: KRConst) or a candidate
+// order whose ranks are in b.rank0 and whose (2T-1, 1/T) table is in L.KR
+// (kr: KRShared), and writes its outputs.  Called by all 64 lanes of a wave.
+//
+// Every recurrence of Sec. IV-F is solved by a lane that owns one item
+// (a segment for Lemma 2, a sub-chain for Theorem 1) and takes the next item
+// from a queue when its own is final, so all lanes stay busy while items
+// remain.  Lemma 2 items are independent.  Sub-chains are coupled only
+// through the H* of the sub-chains whose H* follows Lemma 3 during the
+// iteration (two or more segments): every other H* is a constant.  Those are
+// queued first, each after the ones it reads (executors by the number of
+// higher-priority executors on their core, then rank), then the sub-chains
+// that read none of them, then the rest.  A sub-chain's value is final when
+// an evaluation leaves it unchanged and every Lemma 3 sub-chain it reads is
+// final; until then it is re-evaluated with the current weights.  Every
+// iterate stays below the least fixed point (the system is monotone and
+// starts at 0), so the final values are the least fixed points.
+template <class KR, bool kSbLds>
+__device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_t set, KR kr,
+                              Lds &L, Scratch &S, int8_t *set_sched, int32_t *set_worst,
+                              int64_t *set_worst_R, int64_t *chain_R) {
+  const int lane = threadIdx.x;
+  const int64_t c0 = b.set_chain_off[set];
+  const int C = (int)(b.set_chain_off[set + 1] - c0);
+  const int64_t x0 = b.set_exec_off[set];
+  const int X = (int)(b.set_exec_off[set + 1] - x0);
+  const int64_t a0 = b.set_accel_off[set];
+  const int NA = (int)(b.set_accel_off[set + 1] - a0);
+  const int64_t cb0 = b.set_cb_off[set];
+  const int64_t g0 = b.set_seg_off[set];
+  const int nseg = (int)(b.set_seg_off[set + 1] - g0);
+  const int64_t run0 = b.set_run_off[set];
+  const int nrun = (int)(b.set_run_off[set + 1] - run0);
+  const int32_t u = o.util_permille;
+  const bool full = o.full != 0;
+  const double hop = (double)b.eps_hop[set];
+  const double capm = (double)o.cap_mult;
+  const bool uploaded = KR::kUploaded;
+  double *const SB = kSbLds ? L.SB : S.SB;
+
+  // ---- chain tables in rank order (rank 0 = highest priority) ----
+  for (int c = lane; c < C; c += kWave) {
+    const int rho = b.rank0[c0 + c];
+    L.rank[c] = rho;
+    if (!uploaded) L.KR[rho] = make_double2(b.Kd[c0 + c], b.rcp[c0 + c]);
+    L.Dd[rho] = (double)b.D[c0 + c];
+    L.nrs[rho] = b.chain_nrun[c0 + c] | (b.spin[c0 + c] ? 1 << 16 : 0);
+    L.partial[rho] = 0.0;
+  }
+  for (int i = lane; i < NA * C; i += kWave) {
+    L.Ahat[i] = 0.0;
+    L.Bacc[i] = 0.0;
+    L.level[i] = -1;
+  }
+  for (int i = lane; i < X * C; i += kWave) {
+    L.WP[i] = 0.0;
+    L.Pt[i] = 0.0;
+    SB[i] = 0.0;
+  }
+  for (int e = lane; e < X; e += kWave) {
+    uint32_t m = 0;
+    for (int e2 = 0; e2 < X; ++e2)
+      if ((b.hpx_mask[x0 + e2] >> e) & 1u) m |= 1u << e2;
+    L.lpx[e] = (int32_t)m;
+    L.hpx[e] = (int32_t)b.hpx_mask[x0 + e];
+    L.dfirst[e] = C;
+    L.dspin[e] = 0;
+    L.dmin[e] = 0;
+  }
+  for (int a = lane; a < NA; a += kWave) {
+    L.aek[2 * a] = (double)b.aeps[a0 + a];
+    L.aek[2 * a + 1] = (double)b.akappa[a0 + a];
+  }
+  if (lane == 0) L.misc[0] = 0;  // iteration guard tripped
+  __syncthreads();
+
+  // ---- segments: A* = A + 2 kappa; per chain and accelerator sum and max;
+  //      the Lemma 2 queue (under the uploaded priorities: decreasing rank) ----
+  for (int pos = lane; pos < nseg; pos += kWave) {
+    const int g = uploaded ? b.seg_order[g0 + (nseg - 1 - pos)] : pos;
+    const int a = b.seg_accel[g0 + g];
+    const int rho = L.rank[b.seg_chain[g0 + g]];
+    const double As = scale_time(b.A[g0 + g], u) + 2.0 * L.aek[2 * a + 1];
+    S.segAs[g] = As;
+    S.qs[pos] = make_double2(As, pack2(g, rho | (a << kExecShift)));
+    atomicAdd(&L.Ahat[a * C + rho], As);
+    atomic_max_nonneg(&L.Bacc[a * C + rho], As);
+    L.level[a * C + rho] = 0;  // a user
+  }
+  __syncthreads();
+
+  // ---- buckets (Sec. IV-C) and the same-bucket blocking term of Eq. (3),
+  //      as in the sweep analysis ----
+  for (int a = 0; a < NA; ++a) {
+    int32_t *lv = L.level + a * C;
+    int m = 0;
+    for (int rb = 0; rb < C; rb += kWave) {
+      const int rho = rb + lane;
+      m += (int)__popcll(__ballot(rho < C && lv[rho] >= 0));
+    }
+    const int64_t n = b.buckets[a0 + a];
+    int r0 = 0;
+    for (int rb = 0; rb < C; rb += kWave) {
+      const int rho = rb + lane;
+      const bool us = rho < C && lv[rho] >= 0;
+      const unsigned long long bm = __ballot(us);
+      if (us) lv[rho] = (int)(((int64_t)(r0 + (int)__popcll(bm & lanes_below())) * n) / m);
+      r0 += (int)__popcll(bm);
+    }
+  }
+  __syncthreads();
+  // In place of a user's largest A*: the largest A* of a lower-priority user
+  // of its level.  Levels never decrease down the order, so among the users
+  // below a rank the ones of the smallest level come first; the exclusive
+  // suffix maximum of (smallest level first, then A*) keys gives the term.
+  for (int a = 0; a < NA; ++a) {
+    const int32_t *lv = L.level + a * C;
+    double *bx = L.Bacc + a * C;
+    unsigned long long carry = 0ull;
+    for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
+      const int rho = rb + lane;
+      const int lev = rho < C ? lv[rho] : -1;
+      const unsigned long long key =
+          lev >= 0 ? ((unsigned long long)(kLevTop - lev) << kKeyShift) |
+                         (unsigned long long)bx[rho]
+                   : 0ull;
+      const unsigned long long incl = wave_suffix_max_u64(key);
+      unsigned long long excl = __shfl_down(incl, 1);
+      if (lane == kWave - 1) excl = 0ull;
+      excl = excl > carry ? excl : carry;
+      if (lev >= 0)
+        bx[rho] = (excl != 0ull && kLevTop - (int)(excl >> kKeyShift) == lev)
+                      ? (double)(excl & kKeyMask)
+                      : 0.0;
+      const unsigned long long top = __shfl(incl, 0);
+      carry = top > carry ? top : carry;
+    }
+  }
+  // highest-priority rank with a request of positive length on each
+  // accelerator: a chain of lower rank sees HP accelerator interference
+  for (int a = 0; a < NA; ++a) {
+    int f = C;
+    for (int rb = 0; rb < C; rb += kWave) {
+      const unsigned long long m = __ballot(rb + lane < C && L.Ahat[a * C + rb + lane] > 0.0);
+      if (m) {
+        f = rb + __ffsll((long long)m) - 1;
+        break;
+      }
+    }
+    if (lane == 0) L.misc[1 + a] = f;
+  }
+  __syncthreads();
+
+  // ---- Lemma 2 / Eq. (3): one segment per lane, refilled from the queue
+  //      (the next 64 queue records are loaded one step ahead); a step
+  //      iterates every lane's recurrence up to kMicro times ----
+  {
+    int qnext = 0;
+    bool have = false;
+    int g = 0, rho = 0, a = 0;
+    double hv = 0.0, base = 0.0, capv = 0.0;
+    double2 win = make_double2(0.0, 0.0);
+    if (lane < nseg) win = S.qs[lane];
+    for (int step = 0;; ++step) {
+      const unsigned long long need = __ballot(!have);
+      const int k = (int)__popcll(need & lanes_below());
+      const double wA = __shfl(win.x, k), wP = __shfl(win.y, k);
+      if (!have && qnext + k < nseg) {
+        const int pk = __double2loint(wP);
+        g = __double2hiint(wP);
+        rho = pk & kRankMask;
+        a = pk >> kExecShift;
+        base = wA + L.Bacc[a * C + rho];
+        capv = L.Dd[rho] * capm;
+        hv = 0.0;
+        have = true;
+      }
+      qnext += (int)__popcll(need);
+      if (!wave_any(have)) break;
+      if (qnext + lane < nseg) win = S.qs[qnext + lane];
+      if (step >= kMaxIter) {
+        if (lane == 0) L.misc[0] = 1;
+        break;
+      }
+      const int hend = wave_umax(have ? rho : 0);
+      const int klo = min(wave_umin(have ? rho : C), hend);
+      const double *ah = L.Ahat + a * C;
+      bool done = false;
+      for (int it = 0; it < kMicro; ++it) {
+        double n0 = 0.0, n1 = 0.0;
+        int k2 = 0;
+#pragma unroll 2
+        for (; k2 + 1 < klo; k2 += 2) {
+          const double2 q0 = kr(k2), q1 = kr(k2 + 1);
+          n0 = fma(mu_term(hv, q0.x, q0.y), ah[k2], n0);
+          n1 = fma(mu_term(hv, q1.x, q1.y), ah[k2 + 1], n1);
+        }
+        if (k2 < klo) {
+          const double2 q0 = kr(k2);
+          n0 = fma(mu_term(hv, q0.x, q0.y), ah[k2], n0);
+          ++k2;
+        }
+        for (; k2 + 1 < hend; k2 += 2) {
+          const double2 q0 = kr(k2), q1 = kr(k2 + 1);
+          const double w0 = k2 < rho ? ah[k2] : 0.0;
+          const double w1 = k2 + 1 < rho ? ah[k2 + 1] : 0.0;
+          n0 = fma(mu_term(hv, q0.x, q0.y), w0, n0);
+          n1 = fma(mu_term(hv, q1.x, q1.y), w1, n1);
+        }
+        if (k2 < hend) {
+          const double2 q0 = kr(k2);
+          const double w0 = k2 < rho ? ah[k2] : 0.0;
+          n0 = fma(mu_term(hv, q0.x, q0.y), w0, n0);
+        }
+        if (have && !done) {
+          const double nxt = base + (n0 + n1);
+          if (nxt > capv) {
+            hv = INFINITY;
+            done = true;
+          } else {
+            done = nxt == hv;
+            hv = nxt;
+          }
+        }
+        if (!wave_any(have && !done)) break;
+      }
+      if (have && done) {
+        S.segH[g] = hv;
+        have = false;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- sub-chains: own demand, Lemma 2 sum, Lemma 3 constant, overheads,
+  //      and each callback as a blocking candidate ----
+  const bool safe = o.blocking == PAAM_BLOCK_SAFE;
+  for (int s = lane; s < nrun; s += kWave) {
+    const int64_t rr = run0 + s;
+    const int c = b.run_chain[rr];
+    const int e = b.run_exec[rr];
+    const int rho = L.rank[c];
+    double E = 0.0, L2 = 0.0, A0 = 0.0, eps = 0.0, bmax = 0.0;
+    int delta = 0, accm = 0;
+    for (int j = b.run_cb_lo[rr]; j < b.run_cb_hi[rr]; ++j) {
+      const double Ej = scale_time(b.E[cb0 + j], u);
+      E += Ej;
+      double bj = Ej;
+      for (int64_t gg = b.cb_seg_off[cb0 + j]; gg < b.cb_seg_off[cb0 + j + 1]; ++gg) {
+        const int g = (int)(gg - g0);
+        const int a = b.seg_accel[gg];
+        const double Hg = S.segH[g];
+        const double ea = L.aek[2 * a];
+        L2 += Hg;
+        A0 += S.segAs[g] + L.Bacc[a * C + rho];
+        eps += ea;
+        if (safe) bj += Hg + ea;
+        ++delta;
+        accm |= 1 << a;
+      }
+      bmax = fmax(bmax, bj);
+    }
+    atomic_max_nonneg(&SB[e * C + rho], bmax);
+    const bool needL3 =
+        delta > 0 && (o.bound == PAAM_BOUND_L3 || (o.bound == PAAM_BOUND_MIN && delta >= 2));
+    // H* of a sub-chain that does not need Lemma 3 during the iteration (one
+    // segment: Lemma 3 is the recurrence of Lemma 2 and R >= H at the fixed
+    // point, so H* = L2 + eps; no HP request of positive length: Lemma 3 is
+    // the constant A0 <= L2, also at an unbounded window)
+    bool hp_acc = false;
+    for (int a = 0; a < NA; ++a)
+      if (((accm >> a) & 1) && L.misc[1 + a] < rho) hp_acc = true;
+    double hs0 = delta == 0 ? 0.0 : (hp_acc || o.bound == PAAM_BOUND_L2 ? L2 : A0) + eps;
+    if (needL3) {
+      hs0 = 0.0;  // a start below the fixed point
+      atomicMin(&L.dfirst[e], rho);
+      if (L.nrs[rho] >> 16) atomicAdd(&L.dspin[e], 1);
+      atomicAdd(&L.dmin[__popc((uint32_t)L.hpx[e])], 1);  // per level, before the engine
+    }
+    atomicAdd(&L.WP[e * C + rho], E + hs0);
+    atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
+    S.cst[s] = E + (needL3 ? 0.0 : hs0);
+    S.L2[s] = L2;
+    S.A0[s] = A0;
+    S.eps[s] = eps;
+    S.info[s] = rho | (e << kExecShift) | (accm << kAccShift) | (needL3 ? kNeedL3 : 0) |
+                (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
+  }
+  __syncthreads();
+  // suffix maximum of blocking candidates per executor, lowest priority up
+  // (non-negative doubles order like their bit patterns)
+  for (int e = 0; e < X; ++e) {
+    unsigned long long carry = 0ull;
+    for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
+      const int rho = rb + lane;
+      const unsigned long long v =
+          rho < C ? (unsigned long long)__double_as_longlong(SB[e * C + rho]) : 0ull;
+      unsigned long long incl = wave_suffix_max_u64(v);
+      incl = incl > carry ? incl : carry;
+      if (rho < C) SB[e * C + rho] = __longlong_as_double((long long)incl);
+      carry = __shfl(incl, 0);
+    }
+  }
+  for (int e = lane; e < X; e += kWave) {
+    bool blk = false;
+    for (uint32_t mm = (uint32_t)L.hpx[e]; mm; mm &= mm - 1)
+      if (L.dspin[__ffs(mm) - 1] > 0) blk = true;
+    L.dblk[e] = blk ? 1 : 0;
+  }
+  __syncthreads();
+  for (int s = lane; s < nrun; s += kWave) {
+    const int w = S.info[s];
+    const int rho = w & kRankMask;
+    const int e = (w >> kExecShift) & 31;
+    S.cst[s] += rho + 1 < C ? SB[e * C + rho + 1] : 0.0;
+  }
+  __syncthreads();
+  for (int i = lane; i < X * C; i += kWave) {
+    const int e = i / C, h = i - e * C;
+    double p = 0.0;
+    for (uint32_t m = (uint32_t)L.hpx[e]; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
+    SB[i] = p;
+  }
+  __syncthreads();
+  for (int i = lane; i < X * C; i += kWave) {
+    L.WP[i] += SB[i];
+    L.Pt[i] = SB[i];
+  }
+
+  // ---- the queue of sub-chains: the Lemma 3 sub-chains first (by the number
+  //      of higher-priority executors on their core, then rank), then those
+  //      that read none of them (increasing rank), then the others (decreasing
+  //      rank, written from the back); records (constant part of the
+  //      recurrence, s | packed word) ----
+  int maxlev = 0;
+  for (int e = lane; e < X; e += kWave) maxlev = max(maxlev, __popc((uint32_t)L.hpx[e]));
+  maxlev = wave_umax(maxlev);
+  int n3 = 0;
+  for (int l = 0; l <= maxlev; ++l) n3 += L.dmin[l];
+  if (lane == 0) {
+    int o = 0;
+    for (int l = 0; l <= maxlev; ++l) {
+      const int c = L.dmin[l];
+      L.dspin[l] = o;  // running position of level l
+      o += c;
+    }
+  }
+  wave_sync();
+  {
+    int nind = 0, ndep = 0;
+    for (int sb = 0; sb < nrun; sb += kWave) {
+      const int s = sb + lane;
+      int w = 0, cat = -1;  // level of a Lemma 3 sub-chain; maxlev+1 independent; maxlev+2 other
+      double c = 0.0;
+      if (s < nrun) {
+        w = S.info[s];
+        c = S.cst[s];
+        const int e = (w >> kExecShift) & 31;
+        if (w & kNeedL3) cat = __popc((uint32_t)L.hpx[e]);
+        else cat = ((w & kRankMask) <= L.dfirst[e] && !L.dblk[e]) ? maxlev + 1 : maxlev + 2;
+      }
+      const double2 rec = make_double2(c, pack2(s, w));
+      for (int l = 0; l <= maxlev; ++l) {
+        const unsigned long long m = __ballot(cat == l);
+        if (m) {
+          const int base = L.dspin[l];
+          if (cat == l) S.qr[base + (int)__popcll(m & lanes_below())] = rec;
+          wave_sync();
+          if (lane == 0) L.dspin[l] = base + (int)__popcll(m);
+          wave_sync();
+        }
+      }
+      const unsigned long long mi = __ballot(cat == maxlev + 1);
+      const unsigned long long md = __ballot(cat == maxlev + 2);
+      if (cat == maxlev + 1) S.qr[n3 + nind + (int)__popcll(mi & lanes_below())] = rec;
+      if (cat == maxlev + 2) S.qr[nrun - 1 - (ndep + (int)__popcll(md & lanes_below()))] = rec;
+      nind += (int)__popcll(mi);
+      ndep += (int)__popcll(md);
+    }
+  }
+  __syncthreads();
+
+  // ---- Theorem 1 / Eq. (6): one sub-chain per lane, refilled from the
+  //      queue; the next 64 records are loaded one step ahead ----
+  bool missed = false;
+  {
+    int qnext = 0;
+    bool have = false;
+    int s = 0, rho = 0, e = 0, inf1 = 0, hpxm = 0;
+    double r = 0.0, cst = 0.0, hs = 0.0, L2v = 0.0, A0v = 0.0, epsv = 0.0, capv = 0.0;
+    double2 win = make_double2(0.0, 0.0);
+    if (lane < nrun) win = S.qr[lane];
+    for (int step = 0;; ++step) {
+      const unsigned long long need = __ballot(!have);
+      const int k = (int)__popcll(need & lanes_below());
+      const double wc = __shfl(win.x, k), wP = __shfl(win.y, k);
+      if (!have && qnext + k < nrun) {
+        s = __double2hiint(wP);
+        inf1 = __double2loint(wP);
+        rho = inf1 & kRankMask;
+        e = (inf1 >> kExecShift) & 31;
+        cst = wc;
+        if (inf1 & kNeedL3) {
+          L2v = S.L2[s];
+          A0v = S.A0[s];
+          epsv = S.eps[s];
+        }
+        hpxm = L.hpx[e];
+        capv = L.Dd[rho] * capm;
+        r = 0.0;
+        hs = 0.0;
+        have = true;
+      }
+      const bool l3live = qnext < n3;  // a Lemma 3 sub-chain was queued before this refill
+      qnext += (int)__popcll(need);
+      if (!wave_any(have)) break;
+      if (qnext + lane < nrun) win = S.qr[qnext + lane];
+      if (step >= kMaxIter) {
+        if (lane == 0) L.misc[0] = 1;
+        break;
+      }
+      const bool needL3 = have && (inf1 & kNeedL3) != 0;
+      // Lemma 3 sub-chains not yet final: lowest rank and busy-waiting count
+      // per executor (none once every one of them has left the lanes)
+      bool blocked = false;
+      if (l3live || wave_any(needL3)) {
+        for (int x = lane; x < X; x += kWave) {
+          L.dmin[x] = C;
+          L.dspin[x] = 0;
+        }
+        wave_sync();
+        if (needL3) {
+          atomicMin(&L.dmin[e], rho);
+          if (L.nrs[rho] >> 16) atomicAdd(&L.dspin[e], 1);
+        }
+        wave_sync();
+        blocked = L.dmin[e] < rho;
+        for (uint32_t m = (uint32_t)hpxm; m; m &= m - 1)
+          if (L.dspin[__ffs(m) - 1] > 0) blocked = true;
+      }
+
+      const bool hasP = (inf1 & kHasP) != 0;
+      const int hend = wave_umax(have ? (hasP ? C : rho) : 0);
+      const int accm = (inf1 >> kAccShift) & 0xff;
+      const double *wp = L.WP + e * C;
+      const double *pt = L.Pt + e * C;
+      const double *ah = L.Ahat;
+      const bool l3on = needL3 && (accm & 1) != 0;
+      int e_lo = 0, e_mid = 0;
+      bool anyl3 = false;
+      if (NA == 1) {
+        // The Lemma 3 weight of h is A-hat[h] for a lane that needs Lemma 3
+        // and ranks below h, else 0.  h splits into three ranges: below every
+        // lane's rank (hp weight for all), between the smallest and largest
+        // rank (per-lane selects), above every rank (hpp weight for all).
+        const int rlo = wave_umin(have ? rho : C);
+        const int rhi = wave_umax(have ? rho : -1);
+        e_lo = rlo < hend ? rlo : hend;
+        e_mid = rhi + 1 < hend ? rhi + 1 : hend;
+        anyl3 = wave_any(l3on);
+      }
+      // up to kMicro evaluations with this step's items and weights
+      double rr = r, hh = hs;
+      bool conv = false;
+      for (int it = 0; it < kMicro; ++it) {
+        double I0 = 0.0, I1 = 0.0, l3 = 0.0;
+        int h = 0;
+        if (NA == 1) {
+          if (!anyl3) {
+#pragma unroll 2
+            for (; h + 1 < e_lo; h += 2) {
+              const double2 q0 = kr(h), q1 = kr(h + 1);
+              I0 = fma(mu_term(rr, q0.x, q0.y), wp[h], I0);
+              I1 = fma(mu_term(rr, q1.x, q1.y), wp[h + 1], I1);
+            }
+          } else {
+#pragma unroll 2
+            for (; h + 1 < e_lo; h += 2) {
+              const double2 q0 = kr(h), q1 = kr(h + 1);
+              const double m0 = mu_term(rr, q0.x, q0.y);
+              const double m1 = mu_term(rr, q1.x, q1.y);
+              const double av0 = ah[h], av1 = ah[h + 1];
+              I0 = fma(m0, wp[h], I0);
+              I1 = fma(m1, wp[h + 1], I1);
+              l3 = fma(m0, l3on ? av0 : 0.0, l3);
+              l3 = fma(m1, l3on ? av1 : 0.0, l3);
+            }
+          }
+          if (h < e_lo) {
+            const double2 q0 = kr(h);
+            const double m0 = mu_term(rr, q0.x, q0.y);
+            const double av0 = ah[h];
+            I0 = fma(m0, wp[h], I0);
+            l3 = fma(m0, l3on ? av0 : 0.0, l3);
+            ++h;
+          }
+          for (; h + 1 < e_mid; h += 2) {
+            const double2 q0 = kr(h), q1 = kr(h + 1);
+            const double m0 = mu_term(rr, q0.x, q0.y);
+            const double m1 = mu_term(rr, q1.x, q1.y);
+            double w0 = (h < rho ? wp : pt)[h];
+            double w1 = (h + 1 < rho ? wp : pt)[h + 1];
+            w0 = h == rho ? 0.0 : w0;
+            w1 = h + 1 == rho ? 0.0 : w1;
+            const double av0 = ah[h], av1 = ah[h + 1];
+            I0 = fma(m0, w0, I0);
+            I1 = fma(m1, w1, I1);
+            l3 = fma(m0, (l3on && h < rho) ? av0 : 0.0, l3);
+            l3 = fma(m1, (l3on && h + 1 < rho) ? av1 : 0.0, l3);
+          }
+          if (h < e_mid) {
+            const double2 q0 = kr(h);
+            const double m0 = mu_term(rr, q0.x, q0.y);
+            double w0 = (h < rho ? wp : pt)[h];
+            w0 = h == rho ? 0.0 : w0;
+            const double av0 = ah[h];
+            I0 = fma(m0, w0, I0);
+            l3 = fma(m0, (l3on && h < rho) ? av0 : 0.0, l3);
+            ++h;
+          }
+#pragma unroll 2
+          for (; h + 1 < hend; h += 2) {
+            const double2 q0 = kr(h), q1 = kr(h + 1);
+            I0 = fma(mu_term(rr, q0.x, q0.y), pt[h], I0);
+            I1 = fma(mu_term(rr, q1.x, q1.y), pt[h + 1], I1);
+          }
+          if (h < hend) {
+            const double2 q0 = kr(h);
+            I0 = fma(mu_term(rr, q0.x, q0.y), pt[h], I0);
+            ++h;
+          }
+        }
+        for (; h < hend; ++h) {
+          const double2 q0 = kr(h);
+          const double m0 = mu_term(rr, q0.x, q0.y);
+          double w0 = h < rho ? wp[h] : pt[h];
+          w0 = h == rho ? 0.0 : w0;
+          I0 = fma(m0, w0, I0);
+          if (needL3 && h < rho) {
+            double a0s = 0.0;
+            for (int a = 0; a < NA; ++a)
+              if ((accm >> a) & 1) a0s += L.Ahat[a * C + h];
+            l3 = fma(m0, a0s, l3);
+          }
+        }
+        if (have && !isinf(rr)) {
+          double hsn = hh;
+          if (needL3) {
+            const double L3 = A0v + l3;
+            hsn = (o.bound == PAAM_BOUND_L3 ? L3 : fmin(L2v, L3)) + epsv;
+          }
+          double rn = cst + hsn + (I0 + I1);
+          if (rn > capv) {
+            rn = INFINITY;
+            if (needL3) {
+              // Lemma 3 at an unbounded window: unbounded iff an HP request of
+              // positive length can interfere (then l3 > 0 already)
+              const double L3i = l3 > 0.0 ? INFINITY : A0v;
+              hsn = (o.bound == PAAM_BOUND_L3 ? L3i : fmin(L2v, L3i)) + epsv;
+            }
+          }
+          conv = rn == rr;
+          rr = rn;
+          hh = hsn;
+        }
+        if (!wave_any(have && !conv && !isinf(rr))) break;
+      }
+      if (have) {
+        if (hh != hs) {
+          // H* of the chain on e enters its hp weight on e and, for a
+          // busy-waiting chain, the hp and hpp weights on the core's
+          // lower-priority executors
+          const double dh = hh - hs;
+          atomicAdd(&L.WP[e * C + rho], dh);
+          if (L.nrs[rho] >> 16) {
+            for (uint32_t m = (uint32_t)L.lpx[e]; m; m &= m - 1) {
+              const int e2 = __ffs(m) - 1;
+              atomicAdd(&L.WP[e2 * C + rho], dh);
+              atomicAdd(&L.Pt[e2 * C + rho], dh);
+            }
+          }
+        }
+        if (rr != r) atomicAdd(&L.partial[rho], rr - r);
+        const bool fin = isinf(rr) || (conv && !blocked);
+        r = rr;
+        hs = hh;
+        if (fin) have = false;
+      }
+      wave_sync();
+      if (!full) {
+        // every iterate is a lower bound: a partial end-to-end sum above the
+        // deadline proves the miss
+        const bool miss = L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho];
+        if (wave_any(miss)) {
+          missed = true;
+          break;
+        }
+      }
+    }
+  }
+
+  // ---- end-to-end bounds, verdict, worst chain ----
+  const bool guard = L.misc[0] != 0;
+  bool ok = !missed;
+  if (!missed) {
+    bool late = false;
+    for (int rho = lane; rho < C; rho += kWave) {
+      double R = L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop;
+      if (R > L.Dd[rho] * capm || guard) R = INFINITY;
+      L.partial[rho] = R;
+      if (R > L.Dd[rho]) late = true;
+    }
+    ok = !wave_any(late);
+  }
+  __syncthreads();
+  if (!missed && full && chain_R) {
+    for (int c = lane; c < C; c += kWave) {
+      const double R = L.partial[L.rank[c]];
+      chain_R[c0 + c] = isinf(R) ? PAAM_INF : (int64_t)R;
+    }
+  }
+  // worst chain: the largest R/D (exact cross-multiplication), ties to the
+  // lowest chain index; each lane scans its chains, then a wave reduction
+  int32_t w = -1;
+  double wRd = 0.0;
+  int64_t wD = 1;
+  if (!missed && !guard && (ok || full)) {
+    for (int c = lane; c < C; c += kWave) {
+      const double R = L.partial[L.rank[c]];
+      const int64_t D = b.D[c0 + c];
+      if (w < 0 || ratio_gt(R, D, wRd, wD)) {
+        w = c;
+        wRd = R;
+        wD = D;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const int w2 = __shfl_xor(w, off);
+      const double R2 = __shfl_xor(wRd, off);
+      const int64_t D2 = __shfl_xor(wD, off);
+      bool take = false;
+      if (w2 >= 0) {
+        if (w < 0 || ratio_gt(R2, D2, wRd, wD)) take = true;
+        else if (!ratio_gt(wRd, wD, R2, D2) && w2 < w) take = true;
+      }
+      if (take) {
+        w = w2;
+        wRd = R2;
+        wD = D2;
+      }
+    }
+  }
+  if (lane == 0) {
+    const int64_t wR = (w < 0 || isinf(wRd)) ? PAAM_INF : (int64_t)wRd;
+    set_sched[set] = guard ? -1 : (ok ? 1 : 0);
+    set_worst[set] = w;
+    set_worst_R[set] = wR;
+  }
+  __syncthreads();
+}
+
 __global__ void reset_counter(unsigned long long *counter) { *counter = 0ull; }
 
 template <bool kSbLds>
-__global__ __launch_bounds__(kWave) void wcrt_kernel(WcrtLaunch L) {
+__global__ __launch_bounds__(kWave, 4) void wcrt_kernel(WcrtLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
   Scratch s = carve_scratch(L.scratch + (size_t)blockIdx.x * L.scratch_stride, L.b.max_segs,
                             L.b.max_runs, L.b.max_C, L.b.max_X);
+  // lane 0 claims queue positions; the index is then held in scalar
+  // registers, so every branch on it is uniform across the wave.  The next
+  // position is claimed before the current set is analysed.
+  unsigned long long inext = 0;
+  if (threadIdx.x == 0) inext = atomicAdd(L.counter, 1ull);
+  inext = uniform_u64(inext);
   for (;;) {
-    unsigned long long i = 0;
-    if (threadIdx.x == 0) i = atomicAdd(L.counter, 1ull);
-    i = __shfl(i, 0);
+    const unsigned long long i = inext;
     if (i >= (unsigned long long)L.b.n_sets) break;
+    unsigned long long in2 = 0;
+    if (threadIdx.x == 0) in2 = atomicAdd(L.counter, 1ull);
+    inext = uniform_u64(in2);
     const int64_t set = L.b.work_order[i];
-    analyse_set<kSbLds>(L.b, L.o, set, l, s, L.set_sched, L.set_worst, L.set_worst_R, L.chain_R);
+    const int64_t c0 = L.b.set_chain_off[set];
+    KRConst kr{(const __attribute__((address_space(4))) double *)(L.b.KRr + 2 * c0)};
+    analyse_set_q<KRConst, kSbLds>(L.b, L.o, set, kr, l, s, L.set_sched, L.set_worst,
+                                   L.set_worst_R, L.chain_R);
   }
 }
 
@@ -945,8 +1705,8 @@ __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
 }  // namespace
 
 size_t wave_scratch_bytes(const DevBatch &b) {
-  size_t n = (size_t)b.max_segs * 2 * sizeof(double) + (size_t)b.max_runs * 6 * sizeof(double) +
-             (size_t)b.max_runs * 2 * sizeof(int32_t);
+  size_t n = (size_t)b.max_segs * 4 * sizeof(double) + (size_t)b.max_runs * 8 * sizeof(double) +
+             (size_t)b.max_runs * 2 * sizeof(int32_t) + 16;
   if (sb_in_scratch(b.max_C, b.max_X)) n += (size_t)b.max_X * b.max_C * sizeof(double);
   return (n + 255) & ~(size_t)255;
 }
@@ -959,7 +1719,8 @@ size_t wave_search_bytes(const DevBatch &b) {
 size_t wave_lds_bytes(const DevBatch &b) {
   const size_t Cm = b.max_C, Xm = b.max_X, NAm = b.max_NA > 0 ? b.max_NA : 1;
   const size_t sb = sb_in_scratch((int)Cm, (int)Xm) ? 0 : Xm * Cm;
-  return 8 * (4 * Cm + 2 * NAm * Cm + 2 * Xm * Cm + sb) + 4 * (2 * Cm + NAm * Cm + 5 * Xm + 16);
+  return 8 * (4 * Cm + 2 * NAm * Cm + 2 * Xm * Cm + sb + 2 * NAm) +
+         4 * (2 * Cm + NAm * Cm + 10 * Xm + 16);
 }
 
 int launch_wcrt(const WcrtLaunch &L, void *stream) {
