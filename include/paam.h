@@ -121,6 +121,20 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
                             int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R, void *d_ws,
                             size_t ws_bytes, paam_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * analysis as paam_wcrt_batch, with the same outputs, but with no workspace
+ * argument.  Its scratch is a static device array of 64 MiB per GPU, held
+ * until the process ends; the call allocates nothing.  The number of
+ * persistent waves is limited to what that scratch holds (results do not
+ * depend on it).  PAAM_E_RANGE if one wave of some size class of the batch
+ * needs more scratch than the array holds.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+paam_status paam_wcrt_batch_noalloc(const paam_chainset *cs, const paam_wcrt_opts *o,
+                                    int8_t *set_sched, int32_t *set_worst, int64_t *set_worst_R,
+                                    int64_t *chain_R, paam_stream stream);
+
 /* Schedule autotuner: runs paam_wcrt_batch on this batch with o->waves_per_cu
  * set to each of the n_cand values in cand (1..32), reps times each, timed
  * with HIP events on the stream, and writes the fastest value into

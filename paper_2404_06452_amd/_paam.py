@@ -22,7 +22,8 @@ PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
 
 EXPORTED = (
     "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
-    "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_autotune", "paam_search_bytes",
+    "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_batch_noalloc", "paam_wcrt_autotune",
+    "paam_search_bytes",
     "paam_priority_search", "paam_candidate_bytes", "paam_candidate_wcrt", "paam_features_bytes", "paam_features",
     "paam_mlp_pack", "paam_mlp_forward", "paam_mlp_backward_bytes", "paam_mlp_backward",
     "paam_mlp_adam_step", "paam_score_bytes", "paam_score_candidates",
@@ -75,6 +76,7 @@ def lib():
         L.paam_chainset_info.argtypes = [P, P]
         L.paam_wcrt_bytes.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), ctypes.POINTER(S)]
         L.paam_wcrt_batch.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P, S, P]
+        L.paam_wcrt_batch_noalloc.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P]
         L.paam_wcrt_autotune.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, ctypes.c_int32,
                                           ctypes.c_int32, P, P, P, P, P, S, P,
                                           ctypes.POINTER(ctypes.c_float)]
@@ -105,7 +107,7 @@ def lib():
         L.paam_version.argtypes = []
         L.paam_version.restype = ctypes.c_char_p
         for f in ("paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_info",
-                  "paam_wcrt_bytes", "paam_wcrt_batch", "paam_search_bytes",
+                  "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_batch_noalloc", "paam_search_bytes",
                   "paam_priority_search"):
             getattr(L, f).restype = ctypes.c_int32
         _lib = L
@@ -211,6 +213,13 @@ def paam_wcrt_batch(cs: Chainset, opts: paam_wcrt_opts, out: WcrtOut, ws, stream
                                 _dev_ptr(out.chain_R), ws.data_ptr(), ws.numel(),
                                 _stream_ptr(stream)),
           "paam_wcrt_batch")
+
+
+def paam_wcrt_batch_noalloc(cs: Chainset, opts: paam_wcrt_opts, out: WcrtOut, stream=None) -> None:
+    check(lib().paam_wcrt_batch_noalloc(cs.handle, ctypes.byref(opts), out.set_sched.data_ptr(),
+                                        out.set_worst.data_ptr(), out.set_worst_R.data_ptr(),
+                                        _dev_ptr(out.chain_R), _stream_ptr(stream)),
+          "paam_wcrt_batch_noalloc")
 
 
 def paam_wcrt_autotune(cs: Chainset, opts: paam_wcrt_opts, candidates, reps: int, out: WcrtOut,

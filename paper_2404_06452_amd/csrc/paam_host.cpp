@@ -677,6 +677,51 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
   return PAAM_OK;
 }
 
+paam_status paam_wcrt_batch_noalloc(const paam_chainset *cs, const paam_wcrt_opts *o,
+                                    int8_t *set_sched, int32_t *set_worst, int64_t *set_worst_R,
+                                    int64_t *chain_R, paam_stream stream) {
+  if (!cs) return fail(PAAM_E_INVAL, "chainset is null");
+  paam_status st = check_opts(o);
+  if (st != PAAM_OK) return st;
+  if (!set_sched || !set_worst || !set_worst_R)
+    return fail(PAAM_E_INVAL, "set outputs must not be null");
+  if (o->full && !chain_R) return fail(PAAM_E_INVAL, "full mode needs chain_R");
+  if (paam::wave_lds_bytes(cs->dev) > 160 * 1024)
+    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
+                paam::wave_lds_bytes(cs->dev));
+  // every size class must fit at least one wave into the static scratch
+  for (int k = 0; k < cs->n_classes; ++k) {
+    const size_t per = paam::wave_scratch_bytes(class_view(cs, k));
+    if (per > paam::kNoAllocScratchBytes - 256)
+      return fail(PAAM_E_RANGE,
+                  "sets of %d chains need %zu bytes of scratch per wave; the static scratch "
+                  "holds %zu",
+                  cs->cls[k].max_C, per, paam::kNoAllocScratchBytes - 256);
+  }
+  void *base = nullptr;
+  const int he = paam::noalloc_scratch(&base);
+  if (he != 0) return hip_fail((hipError_t)he, "hipGetSymbolAddress(scratch)");
+  unsigned char *sbase = static_cast<unsigned char *>(base);
+  for (int k = 0; k < cs->n_classes; ++k) {
+    paam::WcrtLaunch L;
+    L.b = class_view(cs, k);
+    L.o = *o;
+    L.set_sched = set_sched;
+    L.set_worst = set_worst;
+    L.set_worst_R = set_worst_R;
+    L.chain_R = o->full ? chain_R : nullptr;
+    L.counter = reinterpret_cast<unsigned long long *>(sbase);  // zeroed by a kernel per launch
+    L.scratch = sbase + 256;
+    L.scratch_stride = paam::wave_scratch_bytes(L.b);
+    L.lds_bytes = paam::wave_lds_bytes(L.b);
+    const int64_t fit = (int64_t)((paam::kNoAllocScratchBytes - 256) / L.scratch_stride);
+    L.grid = (int)std::min<int64_t>(grid_n(L.b.n_sets, o), fit);
+    int e = paam::launch_wcrt(L, stream);
+    if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
+  }
+  return PAAM_OK;
+}
+
 paam_status paam_wcrt_autotune(const paam_chainset *cs, paam_wcrt_opts *o, const int32_t *cand,
                                int32_t n_cand, int32_t reps, int8_t *set_sched,
                                int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R,

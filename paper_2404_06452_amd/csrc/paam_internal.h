@@ -198,6 +198,13 @@ size_t wave_scratch_bytes(const DevBatch &b);
 size_t wave_lds_bytes(const DevBatch &b);
 size_t wave_search_bytes(const DevBatch &b);
 
+// The scratch of paam_wcrt_batch_noalloc: a static device array of this
+// size per GPU (queue counter, then per-wave scratch), and its address on the
+// current device (resolved once per device; returns a hipError_t as int).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+int noalloc_scratch(void **out);
+
 // Launches (defined in paam_kernels.hip); return a hipError_t as int.
 int launch_wcrt(const WcrtLaunch &L, void *stream);
 int launch_search(const SearchLaunch &L, void *stream);

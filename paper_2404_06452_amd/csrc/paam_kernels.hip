@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "paam_device.h"
 #include "paam_internal.h"
 
@@ -1757,6 +1759,37 @@ int launch_search(const SearchLaunch &L, void *stream) {
   else
     hipLaunchKernelGGL(search_kernel<true>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
+}
+
+namespace {
+std::mutex g_scratch_mutex;
+void *g_scratch_dev[kMaxDevices];  // address of `scratch` on each device
+}  // namespace
+
+}  // namespace paam
+
+// Scratch of paam_wcrt_batch_noalloc, for callers that cannot allocate: every
+// GPU the library runs on holds one copy until the process ends.  In host
+// code this name is a host-side stand-in; kernels and copies use the device
+// address that hipGetSymbolAddress returns on each device.
+static __device__ __attribute__((aligned(256))) unsigned char scratch[paam::kNoAllocScratchBytes];
+
+namespace paam {
+
+int noalloc_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return 0;
 }
 
 }  // namespace paam
