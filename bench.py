@@ -381,7 +381,7 @@ def main():
     if wpc == 0:
         # schedule autotuner (library): persistent waves per CU, timed on the
         # middle level of the sweep
-        cands = [4, 6, 8, 10, 12, 16]
+        cands = [4, 8, 12, 16, 20, 24]
         t_opts = _paam.wcrt_opts(full=True, util_permille=levels[len(levels) // 2])
         ws_t = _paam.workspace(_paam.paam_wcrt_bytes(
             dev, _paam.wcrt_opts(full=True, waves_per_cu=max(cands))))

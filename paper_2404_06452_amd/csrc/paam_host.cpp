@@ -633,7 +633,7 @@ paam_status paam_wcrt_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, si
   size_t need = 256;
   for (int k = 0; k < cs->n_classes; ++k) {
     const paam::DevBatch b = class_view(cs, k);
-    need = std::max(need, 256 + (size_t)grid_n(b.n_sets, o) * paam::wave_scratch_bytes(b));
+    need = std::max(need, 256 + (size_t)grid_n(b.n_sets, o) * paam::wcrt_scratch_bytes(b));
   }
   *ws_bytes = need;
   return PAAM_OK;
@@ -654,9 +654,9 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
     return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
   if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
     return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
-  if (paam::wave_lds_bytes(cs->dev) > 160 * 1024)
+  if (paam::wcrt_lds_bytes(cs->dev) > 160 * 1024)
     return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
-                paam::wave_lds_bytes(cs->dev));
+                paam::wcrt_lds_bytes(cs->dev));
   // one launch per size class, in stream order on the same workspace
   for (int k = 0; k < cs->n_classes; ++k) {
     paam::WcrtLaunch L;
@@ -668,8 +668,8 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
     L.chain_R = o->full ? chain_R : nullptr;
     L.counter = static_cast<unsigned long long *>(d_ws);
     L.scratch = static_cast<unsigned char *>(d_ws) + 256;
-    L.scratch_stride = paam::wave_scratch_bytes(L.b);
-    L.lds_bytes = paam::wave_lds_bytes(L.b);
+    L.scratch_stride = paam::wcrt_scratch_bytes(L.b);
+    L.lds_bytes = paam::wcrt_lds_bytes(L.b);
     L.grid = grid_n(L.b.n_sets, o);
     int e = paam::launch_wcrt(L, stream);
     if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
@@ -686,12 +686,12 @@ paam_status paam_wcrt_batch_noalloc(const paam_chainset *cs, const paam_wcrt_opt
   if (!set_sched || !set_worst || !set_worst_R)
     return fail(PAAM_E_INVAL, "set outputs must not be null");
   if (o->full && !chain_R) return fail(PAAM_E_INVAL, "full mode needs chain_R");
-  if (paam::wave_lds_bytes(cs->dev) > 160 * 1024)
+  if (paam::wcrt_lds_bytes(cs->dev) > 160 * 1024)
     return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
-                paam::wave_lds_bytes(cs->dev));
+                paam::wcrt_lds_bytes(cs->dev));
   // every size class must fit at least one wave into the static scratch
   for (int k = 0; k < cs->n_classes; ++k) {
-    const size_t per = paam::wave_scratch_bytes(class_view(cs, k));
+    const size_t per = paam::wcrt_scratch_bytes(class_view(cs, k));
     if (per > paam::kNoAllocScratchBytes - 256)
       return fail(PAAM_E_RANGE,
                   "sets of %d chains need %zu bytes of scratch per wave; the static scratch "
@@ -712,8 +712,8 @@ paam_status paam_wcrt_batch_noalloc(const paam_chainset *cs, const paam_wcrt_opt
     L.chain_R = o->full ? chain_R : nullptr;
     L.counter = reinterpret_cast<unsigned long long *>(sbase);  // zeroed by a kernel per launch
     L.scratch = sbase + 256;
-    L.scratch_stride = paam::wave_scratch_bytes(L.b);
-    L.lds_bytes = paam::wave_lds_bytes(L.b);
+    L.scratch_stride = paam::wcrt_scratch_bytes(L.b);
+    L.lds_bytes = paam::wcrt_lds_bytes(L.b);
     const int64_t fit = (int64_t)((paam::kNoAllocScratchBytes - 256) / L.scratch_stride);
     L.grid = (int)std::min<int64_t>(grid_n(L.b.n_sets, o), fit);
     int e = paam::launch_wcrt(L, stream);

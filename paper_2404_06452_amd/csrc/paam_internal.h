@@ -197,6 +197,10 @@ int launch_adam(float *P, uint16_t *Q, float *M, float *V, const float *G, float
 size_t wave_scratch_bytes(const DevBatch &b);
 size_t wave_lds_bytes(const DevBatch &b);
 size_t wave_search_bytes(const DevBatch &b);
+// The same for the analysis kernel of paam_wcrt_batch (no period table in
+// LDS, blocking table in the wave's scratch).
+size_t wcrt_scratch_bytes(const DevBatch &b);
+size_t wcrt_lds_bytes(const DevBatch &b);
 
 // The scratch of paam_wcrt_batch_noalloc: a static device array of this
 // size per GPU (queue counter, then per-wave scratch), and its address on the

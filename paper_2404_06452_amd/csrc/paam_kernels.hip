@@ -103,10 +103,13 @@ struct Scratch {
   double2 *qr;                             // [max_runs] Theorem 1 queue: (constant, s | packed word)
 };
 
-__device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
+// with_kr: the (2T-1, 1/T) table is in LDS (candidate orders); sb_lds: the
+// blocking table is in LDS.
+__device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm, bool with_kr, bool sb_lds) {
   Lds l;
   double *d = reinterpret_cast<double *>(base);
-  l.KR = reinterpret_cast<double2 *>(d); d += 2 * Cm;
+  l.KR = reinterpret_cast<double2 *>(d);
+  if (with_kr) d += 2 * Cm;
   l.Dd = d; d += Cm;
   l.partial = d; d += Cm;
   l.Ahat = d; d += NAm * Cm;
@@ -114,7 +117,7 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   l.WP = d; d += Xm * Cm;
   l.Pt = d; d += Xm * Cm;
   l.SB = nullptr;
-  if (!sb_in_scratch(Cm, Xm)) {
+  if (sb_lds) {
     l.SB = d;
     d += Xm * Cm;
   }
@@ -136,11 +139,12 @@ __device__ Lds carve_lds(unsigned char *base, int Cm, int Xm, int NAm) {
   return l;
 }
 
-__device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs, int Cm, int Xm) {
+__device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs, int Cm, int Xm,
+                              bool sb_scratch) {
   Scratch s;
   double *d = reinterpret_cast<double *>(base);
   s.SB = nullptr;
-  if (sb_in_scratch(Cm, Xm)) {
+  if (sb_scratch) {
     s.SB = d;
     d += (size_t)Xm * Cm;
   }
@@ -1108,26 +1112,34 @@ __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_
     S.cst[s] += rho + 1 < C ? SB[e * C + rho + 1] : 0.0;
   }
   __syncthreads();
-  for (int i = lane; i < X * C; i += kWave) {
-    const int e = i / C, h = i - e * C;
-    double p = 0.0;
-    for (uint32_t m = (uint32_t)L.hpx[e]; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
-    SB[i] = p;
+  // hpp weights: Pt[e][h] becomes the sum over the core's higher-priority
+  // executors e2 of E + spin() of h on e2 (so far Pt[e2][h]), and enters
+  // WP[e][h].  Executors are rewritten by decreasing number of
+  // higher-priority executors on their core, so every Pt[e2] read is still
+  // the one accumulated above.
+  int maxlev = 0;
+  for (int e = lane; e < X; e += kWave) maxlev = max(maxlev, __popc((uint32_t)L.hpx[e]));
+  maxlev = wave_umax(maxlev);
+  for (int lev = maxlev; lev >= 1; --lev) {
+    for (int i = lane; i < X * C; i += kWave) {
+      const int e = i / C, h = i - e * C;
+      const uint32_t hm = (uint32_t)L.hpx[e];
+      if (__popc(hm) != lev) continue;
+      double p = 0.0;
+      for (uint32_t m = hm; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
+      L.WP[i] += p;
+      L.Pt[i] = p;
+    }
+    wave_sync();
   }
-  __syncthreads();
-  for (int i = lane; i < X * C; i += kWave) {
-    L.WP[i] += SB[i];
-    L.Pt[i] = SB[i];
-  }
+  for (int i = lane; i < X * C; i += kWave)
+    if (L.hpx[i / C] == 0) L.Pt[i] = 0.0;
 
   // ---- the queue of sub-chains: the Lemma 3 sub-chains first (by the number
   //      of higher-priority executors on their core, then rank), then those
   //      that read none of them (increasing rank), then the others (decreasing
   //      rank, written from the back); records (constant part of the
   //      recurrence, s | packed word) ----
-  int maxlev = 0;
-  for (int e = lane; e < X; e += kWave) maxlev = max(maxlev, __popc((uint32_t)L.hpx[e]));
-  maxlev = wave_umax(maxlev);
   int n3 = 0;
   for (int l = 0; l <= maxlev; ++l) n3 += L.dmin[l];
   if (lane == 0) {
@@ -1454,12 +1466,14 @@ __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_
 
 __global__ void reset_counter(unsigned long long *counter) { *counter = 0ull; }
 
-template <bool kSbLds>
-__global__ __launch_bounds__(kWave, 4) void wcrt_kernel(WcrtLaunch L) {
+// The analysis under the uploaded priorities: the (2T-1, 1/T) table is read
+// from the arena, the blocking table lives in the wave's global scratch, so a
+// wave needs only the LDS tables of the iteration.
+__global__ __launch_bounds__(kWave, 5) void wcrt_kernel(WcrtLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
+  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1, false, false);
   Scratch s = carve_scratch(L.scratch + (size_t)blockIdx.x * L.scratch_stride, L.b.max_segs,
-                            L.b.max_runs, L.b.max_C, L.b.max_X);
+                            L.b.max_runs, L.b.max_C, L.b.max_X, true);
   // lane 0 claims queue positions; the index is then held in scalar
   // registers, so every branch on it is uniform across the wave.  The next
   // position is claimed before the current set is analysed.
@@ -1475,7 +1489,7 @@ __global__ __launch_bounds__(kWave, 4) void wcrt_kernel(WcrtLaunch L) {
     const int64_t set = L.b.work_order[i];
     const int64_t c0 = L.b.set_chain_off[set];
     KRConst kr{(const __attribute__((address_space(4))) double *)(L.b.KRr + 2 * c0)};
-    analyse_set_q<KRConst, kSbLds>(L.b, L.o, set, kr, l, s, L.set_sched, L.set_worst,
+    analyse_set_q<KRConst, false>(L.b, L.o, set, kr, l, s, L.set_sched, L.set_worst,
                                    L.set_worst_R, L.chain_R);
   }
 }
@@ -1551,9 +1565,9 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 template <bool kSbLds>
 __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
+  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1, true, kSbLds);
   unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
-  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs, L.b.max_C, L.b.max_X);
+  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs, L.b.max_C, L.b.max_X, !kSbLds);
   SearchSlot q = carve_slot(wbase + L.analysis_stride, L.b.max_C);
   paam_wcrt_opts o = L.o.wcrt;
   o.full = 0;
@@ -1658,9 +1672,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
 template <bool kSbLds>
 __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1);
+  Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1, true, kSbLds);
   unsigned char *wbase = L.scratch + (size_t)blockIdx.x * L.scratch_stride;
-  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs, L.b.max_C, L.b.max_X);
+  Scratch s = carve_scratch(wbase, L.b.max_segs, L.b.max_runs, L.b.max_C, L.b.max_X, !kSbLds);
   SearchSlot q = carve_slot(wbase + L.analysis_stride, L.b.max_C);
   // Grid-stride over the pairs: the item index derives from blockIdx only, so
   // it is wave-uniform by construction.  (With a lane-0 queue fetch, the path
@@ -1706,11 +1720,22 @@ __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
 
 }  // namespace
 
-size_t wave_scratch_bytes(const DevBatch &b) {
+static size_t scratch_bytes(const DevBatch &b, bool sb_scratch) {
   size_t n = (size_t)b.max_segs * 4 * sizeof(double) + (size_t)b.max_runs * 8 * sizeof(double) +
              (size_t)b.max_runs * 2 * sizeof(int32_t) + 16;
-  if (sb_in_scratch(b.max_C, b.max_X)) n += (size_t)b.max_X * b.max_C * sizeof(double);
+  if (sb_scratch) n += (size_t)b.max_X * b.max_C * sizeof(double);
   return (n + 255) & ~(size_t)255;
+}
+
+static size_t lds_bytes(const DevBatch &b, bool with_kr, bool sb_lds) {
+  const size_t Cm = b.max_C, Xm = b.max_X, NAm = b.max_NA > 0 ? b.max_NA : 1;
+  const size_t d = (with_kr ? 2 * Cm : 0) + 2 * Cm + 2 * NAm * Cm + 2 * Xm * Cm +
+                   (sb_lds ? Xm * Cm : 0) + 2 * NAm;
+  return 8 * d + 4 * (2 * Cm + NAm * Cm + 10 * Xm + 16);
+}
+
+size_t wave_scratch_bytes(const DevBatch &b) {
+  return scratch_bytes(b, sb_in_scratch(b.max_C, b.max_X));
 }
 
 size_t wave_search_bytes(const DevBatch &b) {
@@ -1719,11 +1744,12 @@ size_t wave_search_bytes(const DevBatch &b) {
 }
 
 size_t wave_lds_bytes(const DevBatch &b) {
-  const size_t Cm = b.max_C, Xm = b.max_X, NAm = b.max_NA > 0 ? b.max_NA : 1;
-  const size_t sb = sb_in_scratch((int)Cm, (int)Xm) ? 0 : Xm * Cm;
-  return 8 * (4 * Cm + 2 * NAm * Cm + 2 * Xm * Cm + sb + 2 * NAm) +
-         4 * (2 * Cm + NAm * Cm + 10 * Xm + 16);
+  return lds_bytes(b, true, !sb_in_scratch(b.max_C, b.max_X));
 }
+
+size_t wcrt_scratch_bytes(const DevBatch &b) { return scratch_bytes(b, true); }
+
+size_t wcrt_lds_bytes(const DevBatch &b) { return lds_bytes(b, false, false); }
 
 int launch_wcrt(const WcrtLaunch &L, void *stream) {
   hipStream_t st = (hipStream_t)stream;
@@ -1731,10 +1757,7 @@ int launch_wcrt(const WcrtLaunch &L, void *stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   if (L.b.n_sets == 0) return 0;
-  if (sb_in_scratch(L.b.max_C, L.b.max_X))
-    hipLaunchKernelGGL(wcrt_kernel<false>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
-  else
-    hipLaunchKernelGGL(wcrt_kernel<true>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  hipLaunchKernelGGL(wcrt_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
 }
 
