@@ -330,6 +330,157 @@ def large_section(args, torch, log, net):
     return res
 
 
+def ablation_section(torch, dev, levels, outs, ws, stream, log):
+    """Lemma 2 alone, Lemma 3 alone and their minimum (Sec. IV-F: neither
+    bound dominates the other).  Per utilisation level: schedulable fraction
+    under each, and the share of chains whose end-to-end bound each single
+    bound makes larger than the minimum (PAAM_INF counts as larger than any
+    finite bound)."""
+    from paper_2404_06452_amd import _paam
+    res = {}
+    n_chains = int(dev.n_chains)
+    o_l2 = _paam.WcrtOut(dev, True)
+    o_l3 = _paam.WcrtOut(dev, True)
+    for li, u in enumerate(levels):
+        for out, bound in ((o_l2, _paam.PAAM_BOUND_L2), (o_l3, _paam.PAAM_BOUND_L3)):
+            o = _paam.wcrt_opts(full=True, util_permille=u, bound=bound)
+            with torch.cuda.stream(stream):
+                _paam.paam_wcrt_batch(dev, o, out, ws, stream)
+        torch.cuda.synchronize()
+        rm = outs[li].chain_R[:n_chains]
+        r2 = o_l2.chain_R[:n_chains]
+        r3 = o_l3.chain_R[:n_chains]
+        assert bool((rm <= r2).all()) and bool((rm <= r3).all()), "min bound above a single bound"
+        res[str(u / 1000)] = {
+            "schedulable_frac": {"min": float((outs[li].set_sched == 1).float().mean()),
+                                 "lemma2_only": float((o_l2.set_sched == 1).float().mean()),
+                                 "lemma3_only": float((o_l3.set_sched == 1).float().mean())},
+            "chains_lemma2_only_larger": float((r2 > rm).float().mean()),
+            "chains_lemma3_only_larger": float((r3 > rm).float().mean()),
+            "chains_lemma2_below_lemma3": float((r2 < r3).float().mean()),
+            "chains_lemma3_below_lemma2": float((r3 < r2).float().mean()),
+        }
+    log("ablation: level 0.10 L2-only larger %.3f, L3-only larger %.3f of chains" % (
+        res[str(levels[0] / 1000)]["chains_lemma2_only_larger"],
+        res[str(levels[0] / 1000)]["chains_lemma3_only_larger"]))
+    del o_l2, o_l3
+    return {"levels": res,
+            "note": "every chain's bound of the sweep under Lemma 2 alone and Lemma 3 alone, "
+                    "compared with their minimum (the analysis above); a single bound is never "
+                    "below the minimum (asserted)"}
+
+
+def study_section(args, torch, log, net):
+    """The analytical study of the paper's Sec. V: schedulability against the
+    number of chains (4 callbacks per chain, accelerator : CPU utilisation 1:1
+    per chain) and against that ratio (1:9 ... 7:3 at 8 chains), 1,000 sets
+    per point, on the batched analysis.  On the 8-chain 1:1 point, plain and
+    guided priority-order search.  Bit-exact parity of every point against the
+    CPU oracle is a GPU test (tests/test_gpu_study.py)."""
+    from paper_2404_06452_amd import _paam, chaingen
+
+    stream = torch.cuda.Stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    n = args.study_sets
+    t0 = time.perf_counter()
+
+    def point(n_chains, acc, cpu):
+        cs = chaingen.generate(chaingen.study_params(n_chains, acc, cpu), n)
+        dev = _paam.Chainset(cs, device="cuda:0")
+        o = _paam.wcrt_opts(full=False)
+        out = _paam.WcrtOut(dev, False)
+        ws = _paam.workspace(_paam.paam_wcrt_bytes(dev, o))
+        dt = timed(lambda: _paam.paam_wcrt_batch(dev, o, out, ws, stream))
+        frac = float((out.set_sched == 1).float().mean())
+        return dev, frac, dt
+
+    by_chains, t_an = {}, 0.0
+    for c in chaingen.STUDY_CHAINS:
+        dev, frac, dt = point(c, 1, 1)
+        by_chains[str(c)] = frac
+        t_an += dt
+        dev.free()
+    by_ratio = {}
+    for acc, cpu in chaingen.STUDY_RATIOS:
+        dev, frac, dt = point(chaingen.STUDY_RATIO_CHAINS, acc, cpu)
+        by_ratio["%d:%d" % (acc, cpu)] = frac
+        t_an += dt
+        dev.free()
+    vc, vr = list(by_chains.values()), list(by_ratio.values())
+    res = {
+        "workload": "%d sets per point; chains of 4 callbacks, each with one accelerator "
+                    "segment; one accelerator; each chain on its own single-threaded executor "
+                    "and core; chain utilisations UUniFast at %.2f per chain; periods "
+                    "log-uniform 10-1000 ms; rate-monotonic priorities" % (
+                        n, chaingen.STUDY_CHAIN_UTIL),
+        "schedulable_frac_by_chains_ratio_1_1": by_chains,
+        "schedulable_frac_by_ratio_%d_chains" % chaingen.STUDY_RATIO_CHAINS: by_ratio,
+        "trend_chains_non_increasing": all(b <= a + 0.02 for a, b in zip(vc, vc[1:])),
+        "trend_ratio_non_increasing": all(b <= a + 0.02 for a, b in zip(vr, vr[1:])),
+        "analysis_ms_total": t_an * 1e3,
+        "parity": "tests/test_gpu_study.py compares every set of every point with the oracle",
+    }
+    log("study: by chains %s | by ratio %s" % (
+        " ".join("%.2f" % v for v in vc), " ".join("%.2f" % v for v in vr)))
+    if net is not None:
+        # priority-order search on sets that can be admitted: the 8-chain,
+        # 1:1 point, 256 candidate orders per set
+        n_cand, top_k, seed = 256, 16, 2404
+        cs = chaingen.generate(chaingen.study_params(chaingen.STUDY_RATIO_CHAINS, 1, 1), n)
+        dev = _paam.Chainset(cs, device="cuda:0")
+        out = _paam.SearchOut(dev)
+        scores = torch.empty(cs.n_sets * n_cand, dtype=torch.float32, device="cuda:0")
+
+        def search(k, guided, fallback=True):
+            o = _paam.search_opts(k, seed, guided=guided, top_k=top_k, fallback=fallback,
+                                  scores=scores if guided else None)
+            ws = _paam.workspace(_paam.paam_search_bytes(dev, o))
+            dt = timed(lambda: _paam.paam_priority_search(dev, o, out, ws, stream))
+            return dt, out.found.cpu().numpy(), out.n_exact.cpu().numpy()
+
+        so = _paam.search_opts(n_cand, seed)
+        sws = _paam.workspace(_paam.paam_score_bytes(dev, so))
+        t_sc = timed(lambda: _paam.paam_score_candidates(dev, so, net.params, net.packed, scores,
+                                                         sws, stream))
+        t_p, f_p, e_p = search(n_cand, False)
+        t_g, f_g, e_g = search(n_cand, True, False)
+        t_i, f_i, e_i = search(top_k, False)
+        fp = int((f_p >= 0).sum())
+        res["search_8_chains"] = {
+            "candidates": n_cand, "top_k": top_k,
+            "rm_schedulable_frac": float((f_p == 0).mean()),
+            "plain": {"found_frac": float((f_p >= 0).mean()),
+                      "mean_exact_evals": float(e_p.mean()), "ms": t_p * 1e3},
+            "guided_top_k_only": {"found_frac": float((f_g >= 0).mean()),
+                                  "found_vs_plain": float((f_g >= 0).sum() / fp) if fp else None,
+                                  "mean_exact_evals": float(e_g.mean()),
+                                  "ms": (t_sc + t_g) * 1e3},
+            "first_k_in_index_order": {"found_frac": float((f_i >= 0).mean()),
+                                       "found_vs_plain": (float((f_i >= 0).sum() / fp)
+                                                          if fp else None),
+                                       "mean_exact_evals": float(e_i.mean())},
+            "network": "the ranking network trained in the search section",
+        }
+        log("study search: plain found %.3f (RM %.3f) | guided top-%d %.3f | first %d %.3f" % (
+            res["search_8_chains"]["plain"]["found_frac"],
+            res["search_8_chains"]["rm_schedulable_frac"], top_k,
+            res["search_8_chains"]["guided_top_k_only"]["found_frac"], top_k,
+            res["search_8_chains"]["first_k_in_index_order"]["found_frac"]))
+        dev.free()
+    res["setup_s"] = time.perf_counter() - t0
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +499,8 @@ def main():
                     help="sets of 256 chains for the large-set section (0 skips it)")
     ap.add_argument("--large-plain-sets", type=int, default=500,
                     help="sets of the large batch searched plainly for comparison")
+    ap.add_argument("--study-sets", type=int, default=1000,
+                    help="sets per point of the analytical study (0 skips it)")
     ap.add_argument("--large-util", type=int, default=0,
                     help="optional second utilisation scale of the large-set section, in "
                          "permille (0: the workload's utilisation only)")
@@ -456,6 +609,10 @@ def main():
     torch.cuda.synchronize()
     verdict_rate = analyses / (time.perf_counter() - t1)
 
+    # double-bounding ablation: the sweep again with Lemma 2 only and with
+    # Lemma 3 only (every chain's bound), against the min of both used above
+    ablation = ablation_section(torch, dev, levels, outs, ws, stream, log)
+
     # CPU oracle on a bounded sample of the same sweep (single thread), and
     # bit-exact comparison of the GPU outputs on that sample
     import oracle
@@ -505,6 +662,7 @@ def main():
         "parity": {"sampled_analyses": n_s * len(levels), "mismatches": mism,
                    "compared": "set verdicts and every chain bound vs the CPU oracle"},
         "verdict_mode_analyses_per_s": verdict_rate,
+        "bound_ablation": ablation,
         "schedulable_fraction_by_level": dict(zip([u / 1000 for u in levels], sched_rate)),
         "roofline": {
             "bound": "alu",
@@ -532,6 +690,10 @@ def main():
         torch.cuda.empty_cache()
         if args.large_sets > 0:
             line["large"] = large_section(args, torch, log, net)
+    else:
+        net = None
+    if args.study_sets > 0:
+        line["study"] = study_section(args, torch, log, net)
     print(json.dumps(line), flush=True)
     if mism:
         sys.exit(1)

@@ -23,6 +23,10 @@ preset says otherwise):
 * ``search`` - 16 chains x 2-8 callbacks, 4 executors, U ~ U(0.5, 0.9).
 * ``large``  - 256 chains x 2-32 callbacks, 8 executors, U ~ U(0.3, 0.95),
   50 % segments.
+* ``study_params(n, acc, cpu)`` - the analytical study of Sec. V: n chains
+  of 4 callbacks, each with one segment, accelerator : CPU utilisation
+  acc : cpu per chain, one executor per chain on its own core, UUniFast at
+  0.05 per chain (readings documented at STUDY_CHAIN_UTIL).
 * ``small_overheads`` - ``small`` with the paper's measured overheads: 6
   buckets (Sec. IV-C), epsilon = 391 us (Sec. V-C, worst request overhead),
   kappa = 129.18 us (Sec. V-C table, worst preemption delay), hop cost =
@@ -62,6 +66,8 @@ class GenParams:
     eps: int = 0
     kappa: int = 0
     eps_hop: int = 0
+    exec_per_chain: bool = False  # every callback of chain c on executor c mod n_exec
+    own_cores: bool = False       # every executor alone on its core
 
     def replace(self, **kw) -> "GenParams":
         return dataclasses.replace(self, **kw)
@@ -78,6 +84,30 @@ PRESETS["small_overheads"] = PRESETS["small"].replace(
 
 # utilisation levels of the sweep, in permille: 0.10, 0.15, ..., 0.95
 SWEEP_LEVELS = tuple(range(100, 951, 50))
+
+# Analytical study of the paper's Sec. V (schedulability against the number of
+# chains, and against the accelerator : CPU utilisation ratio).  The paper
+# fixes 4 callbacks per chain, one accelerator, random periods and the
+# per-chain ratio (1:1, then 1:9 ... 7:3) with each chain's utilisation split
+# equally over its callbacks.  Readings for what it leaves open: every
+# callback carries one segment (its accelerator share of the callback's
+# utilisation is the ratio); each chain runs on a single-threaded executor of
+# its own, alone on its core, so chains contend only on the shared
+# accelerator; chain utilisations come from UUniFast at 0.05 per chain.
+STUDY_CHAIN_UTIL = 0.05
+STUDY_CHAINS = tuple(range(1, 17))
+STUDY_RATIOS = ((1, 9), (2, 8), (3, 7), (4, 6), (5, 5), (6, 4), (7, 3))
+STUDY_RATIO_CHAINS = 8
+
+
+def study_params(n_chains: int, acc: int = 1, cpu: int = 1) -> GenParams:
+    """Generator of the analytical study: n_chains chains of 4 callbacks,
+    accelerator : CPU utilisation acc : cpu per chain."""
+    u = STUDY_CHAIN_UTIL * n_chains
+    f = acc / (acc + cpu)
+    return GenParams(SEED_BASE + 5 + 1000 * n_chains + 100 * acc + cpu, (n_chains, n_chains),
+                     (4, 4), n_chains, (u, u), (1.0, 1.0), (f, f), exec_per_chain=True,
+                     own_cores=True)
 
 
 @dataclass
@@ -199,6 +229,7 @@ class _Params(ctypes.Structure):
         ("T_lo", ctypes.c_double), ("T_hi", ctypes.c_double),
         ("spin_prob", ctypes.c_double),
         ("eps", ctypes.c_int64), ("kappa", ctypes.c_int64), ("eps_hop", ctypes.c_int64),
+        ("exec_per_chain", ctypes.c_int32), ("own_cores", ctypes.c_int32),
     ]
 
 
@@ -257,7 +288,8 @@ def generate(params: GenParams | str, n_sets: int, set_begin: int = 0,
         n_buckets=params.n_buckets, util_lo=params.util[0], util_hi=params.util[1],
         pseg_lo=params.pseg[0], pseg_hi=params.pseg[1], frac_lo=params.frac[0],
         frac_hi=params.frac[1], T_lo=params.T[0], T_hi=params.T[1],
-        spin_prob=params.spin_prob, eps=params.eps, kappa=params.kappa, eps_hop=params.eps_hop)
+        spin_prob=params.spin_prob, eps=params.eps, kappa=params.kappa, eps_hop=params.eps_hop,
+        exec_per_chain=1 if params.exec_per_chain else 0, own_cores=1 if params.own_cores else 0)
     counts = np.zeros((n_sets, 3), dtype=np.int64)
     if lib.chaingen_count(ctypes.byref(p), _ptr(counts)) != 0:
         raise ValueError("invalid generator parameters")

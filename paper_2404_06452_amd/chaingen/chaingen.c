@@ -37,6 +37,8 @@ typedef struct {
   double T_lo, T_hi;              /* period range in ns, log-uniform */
   double spin_prob;               /* P(chain busy-waits during its accelerator requests) */
   int64_t eps, kappa, eps_hop;    /* per-request overhead, preemption cost, hop cost (ns) */
+  int32_t exec_per_chain;         /* 1: every callback of chain c on executor c mod n_exec */
+  int32_t own_cores;              /* 1: every executor alone on its core (else pairs share one) */
 } chaingen_params;
 
 #define GAMMA 0x9E3779B97F4A7C15ULL
@@ -185,7 +187,8 @@ int chaingen_fill(const chaingen_params *p, const chaingen_out *o) {
           int64_t W = (int64_t)llround(W_real);
           if (W < 1) W = 1;
           const int32_t eta = draw_nseg(p, &s, sh.pseg);
-          o->exec[cb] = (int16_t)rng_int(&v, 0, p->n_exec - 1);
+          const int32_t ex = (int32_t)rng_int(&v, 0, p->n_exec - 1);
+          o->exec[cb] = (int16_t)(p->exec_per_chain ? c % p->n_exec : ex);
           o->cb_seg_off[cb] = sg;
           int64_t Atot = 0;
           if (eta > 0) {
@@ -217,9 +220,10 @@ int chaingen_fill(const chaingen_params *p, const chaingen_out *o) {
       }
       for (int32_t r = 0; r < C; ++r) o->prio[c0 + order[r]] = C - r;
 
-      /* executors: pairs share a core; process priority decreases with the index */
+      /* executors: pairs share a core (or each has its own); process priority
+         decreases with the index */
       for (int32_t e = 0; e < p->n_exec; ++e) {
-        o->exec_core[i * p->n_exec + e] = (int16_t)(e / 2);
+        o->exec_core[i * p->n_exec + e] = (int16_t)(p->own_cores ? e : e / 2);
         o->exec_prio[i * p->n_exec + e] = p->n_exec - e;
       }
       for (int32_t a = 0; a < p->n_accel; ++a) {

@@ -54,3 +54,22 @@ def test_sweep_ranges():
     assert set(np.unique(cs.exec).tolist()) == {0, 1, 2, 3}
     assert cs.exec_core.tolist()[:4] == [0, 0, 1, 1]
     assert cs.exec_prio.tolist()[:4] == [4, 3, 2, 1]
+
+
+def test_study_recipe_structure():
+    """The analytical study's sets: 4 callbacks per chain, one segment each,
+    accelerator share of each callback's WCET = the ratio (to rounding), each
+    chain on its own executor alone on its core."""
+    from paper_2404_06452_amd import chaingen
+    for n, (acc, cpu) in ((1, (1, 1)), (8, (1, 9)), (8, (7, 3)), (16, (1, 1))):
+        cs = chaingen.generate(chaingen.study_params(n, acc, cpu), 20)
+        for s in range(cs.n_sets):
+            d = cs.set_dict(s)
+            assert len(d["chains"]) == n
+            assert d["exec_core"] == list(range(n))
+            for c, ch in enumerate(d["chains"]):
+                assert len(ch["cbs"]) == 4
+                for cb in ch["cbs"]:
+                    assert cb["exec"] == c and len(cb["segs"]) == 1
+                    A, W = cb["segs"][0][0], cb["E"] + cb["segs"][0][0]
+                    assert abs(A - acc / (acc + cpu) * W) <= 1.0
