@@ -56,8 +56,7 @@ def measured_traffic(n_sets, waves_per_cu):
     import hashlib
     with open(KERNEL_SRC, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if (sha != TRAFFIC["sha256"] or n_sets != TRAFFIC["sets"]
-            or waves_per_cu != TRAFFIC["waves_per_cu"]):
+    if sha != TRAFFIC["sha256"] or n_sets != TRAFFIC["sets"]:
         return None
     return TRAFFIC["bytes_per_launch"]
 
@@ -330,6 +329,71 @@ def large_section(args, torch, log, net):
     return res
 
 
+def allcore_parity(args, cs, levels, outs, oracle, log):
+    """The oracle on every host core over the first --allcore-sets sets at all
+    levels (one single-threaded analysis per set, sets spread over a thread
+    pool), compared bit-exactly with the GPU's outputs of the sweep."""
+    n = min(args.allcore_sets, cs.n_sets)
+    if n <= 0:
+        return None
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    nc = int(cs.set_chain_off[n])
+    mism, t0 = 0, time.perf_counter()
+    for li, u in enumerate(levels):
+        r = oracle.wcrt(cs, full=True, util_permille=u, sets=(0, n), threads=threads)
+        mism += int(np.sum(outs[li].set_sched[:n].cpu().numpy() != r["sched"][:n]))
+        mism += int(np.sum(outs[li].chain_R[:nc].cpu().numpy() != r["chain_R"][:nc]))
+    wall = time.perf_counter() - t0
+    log("oracle on %d threads: %d analyses in %.1f s; mismatches %d" % (
+        threads, n * len(levels), wall, mism))
+    return {"sets_per_level": n, "levels": len(levels), "analyses": n * len(levels),
+            "threads": threads, "nproc": os.cpu_count(), "wall_s": wall,
+            "analyses_per_s": n * len(levels) / wall, "mismatches": mism}
+
+
+def other_cpu_legs(args, oracle, log):
+    """The single-threaded oracle on the other workloads' fixed samples: the
+    small sets (all 1,000, full mode), plain search over 256 candidate orders
+    on 1,000 search sets, and the uploaded order of 100 large sets."""
+    from paper_2404_06452_amd import chaingen
+    res = {}
+    cs = chaingen.generate("small", 1000)
+    t0 = time.perf_counter()
+    oracle.wcrt(cs, full=True)
+    dt = time.perf_counter() - t0
+    res["small_1000_sets"] = {"analyses_per_s": 1000 / dt, "s": dt}
+    cs = chaingen.generate("search", 1000)
+    t0 = time.perf_counter()
+    r = oracle.search(cs, 256, 2404)
+    dt = time.perf_counter() - t0
+    res["search_1000_sets_x256"] = {"sets_per_s": 1000 / dt, "s": dt,
+                                    "analyses": int(r["n_eval"].sum())}
+    if args.large_sets > 0:
+        cs = chaingen.generate("large", 100)
+        t0 = time.perf_counter()
+        oracle.wcrt(cs, full=False)
+        dt = time.perf_counter() - t0
+        res["large_100_sets"] = {"analyses_per_s": 100 / dt, "s": dt}
+    log("oracle, other workloads: %s" % ", ".join("%s %.1f s" % (k, v["s"]) for k, v in res.items()))
+    return res
+
+
+def manifest(args, torch, _paam):
+    """What produced the line: arguments, seeds, host and device."""
+    from paper_2404_06452_amd import chaingen
+    p = torch.cuda.get_device_properties(0)
+    return {
+        "args": vars(args),
+        "seeds": {k: v.seed for k, v in chaingen.PRESETS.items()},
+        "nproc": os.cpu_count(),
+        "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+        "gpu": {"name": p.name, "arch": getattr(p, "gcnArchName", None),
+                "compute_units": p.multi_processor_count, "memory_bytes": p.total_memory},
+        "torch": torch.__version__, "hip": getattr(torch.version, "hip", None),
+        "libpaam": _paam.lib().paam_version().decode(),
+    }
+
+
 def ablation_section(torch, dev, levels, outs, ws, stream, log):
     """Lemma 2 alone, Lemma 3 alone and their minimum (Sec. IV-F: neither
     bound dominates the other).  Per utilisation level: schedulable fraction
@@ -487,7 +551,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sets", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1000, help="sets per level for the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=10000,
+                    help="sets per level for the single-threaded oracle")
+    ap.add_argument("--allcore-sets", type=int, default=100000,
+                    help="sets per level compared with the oracle on all host cores (0 skips)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--search-sets", type=int, default=100_000)
@@ -495,7 +562,7 @@ def main():
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--train-epochs", type=int, default=2)
     ap.add_argument("--skip-search", action="store_true")
-    ap.add_argument("--large-sets", type=int, default=10000,
+    ap.add_argument("--large-sets", type=int, default=100000,
                     help="sets of 256 chains for the large-set section (0 skips it)")
     ap.add_argument("--large-plain-sets", type=int, default=500,
                     help="sets of the large batch searched plainly for comparison")
@@ -539,10 +606,15 @@ def main():
         ws_t = _paam.workspace(_paam.paam_wcrt_bytes(
             dev, _paam.wcrt_opts(full=True, waves_per_cu=max(cands))))
         best_ms = _paam.paam_wcrt_autotune(dev, t_opts, cands, 1, outs[0], ws_t, stream)
-        wpc = int(t_opts.waves_per_cu)
-        tune = {"candidates_waves_per_cu": cands, "chosen": wpc, "best_ms": best_ms,
-                "level": levels[len(levels) // 2] / 1000}
-        log("autotune: %d waves per CU (%.1f ms per launch)" % (wpc, best_ms))
+        wpc = int(t_opts.waves_per_cu)  # 0: the per-class choices stored in the handle
+        sched = _paam.paam_wcrt_schedule(dev)
+        tune = {"candidates_waves_per_cu": cands, "candidates_evals_per_step": [1, 2, 3],
+                "per_class": [{"max_chains": c, "sets": n, "waves_per_cu": w,
+                               "evals_per_step": m} for c, n, w, m in sched],
+                "best_ms_per_level": best_ms, "level": levels[len(levels) // 2] / 1000}
+        log("autotune: %s (%.1f ms per level)" % (
+            ", ".join("<=%d chains: %d waves/CU x %d" % (c, w, m) for c, n, w, m in sched),
+            best_ms))
         del ws_t
     opts = [_paam.wcrt_opts(full=True, util_permille=u, waves_per_cu=wpc) for u in levels]
     ws = _paam.workspace(max(_paam.paam_wcrt_bytes(dev, o) for o in opts))
@@ -599,7 +671,7 @@ def main():
     log("%.1f ms/step (events %.1f), %.3g analyses/s" % (ms_per_step, np.mean(step_ms), value))
 
     # verdict-only mode (stops a set at its first missed deadline), one sweep
-    vopts = [_paam.wcrt_opts(full=False, util_permille=u) for u in levels]
+    vopts = [_paam.wcrt_opts(full=False, util_permille=u, waves_per_cu=wpc) for u in levels]
     vout = _paam.WcrtOut(dev, False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -631,6 +703,19 @@ def main():
         sched_rate.append(float(outs[li].set_sched.float().mean().item()))
     cpu_rate = n_s * len(levels) / cpu_time
     log("oracle: %d analyses in %.1f s; mismatches %d" % (n_s * len(levels), cpu_time, mism))
+    allcore = allcore_parity(args, cs, levels, outs, oracle, log)
+    mism += allcore["mismatches"] if allcore else 0
+    other_cpu = other_cpu_legs(args, oracle, log)
+
+    # HBM view: the problem statement's bytes (every input field of every set
+    # once) plus the outputs, per level, over the level's time
+    out_bytes = cs.n_sets * (1 + 4 + 8) + cs.n_chains * 8
+    level_bytes = cs.nbytes() + out_bytes
+    hbm_rate = level_bytes / (launch_ms * n_classes * 1e-3)
+    hbm = {"algorithmic_bytes_per_level": level_bytes, "achieved_GBps": hbm_rate / 1e9,
+           "frac_of_8TBps": hbm_rate / 8e12, "frac_of_measured_copy": hbm_rate / (copy_gbs * 1e9),
+           "note": "input fields of the problem statement read once per level plus outputs; "
+                   "the analysis is ALU-bound (roofline)"}
 
     # roofline: algorithmic terms per launch (oracle count per analysis on the
     # sample x sets per launch) over the average launch duration
@@ -681,7 +766,11 @@ def main():
             "value": cpu_rate, "unit": "analyses/s", "cores": 1, "kind": "oracle",
             "sample": "first %d sets of the same batch at all %d levels (%d analyses), full "
                       "mode" % (n_s, len(levels), n_s * len(levels)),
+            "all_core_parity": allcore,
+            "other_workloads_single_core": other_cpu,
         },
+        "hbm": hbm,
+        "manifest": manifest(args, torch, _paam),
     }
     if not args.skip_search:
         del graph, eager, dev, outs, ws, vout

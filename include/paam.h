@@ -82,7 +82,12 @@ paam_status paam_chainset_bytes(const paam_chainset_host *h, size_t *arena_bytes
  * aligned).  Blocks until the copy is done.  *out must be released with
  * paam_chainset_free; the arena must outlive it.  Limits per set: 1..4096
  * chains, 1..32 executors, 0..8 accelerators, 65535 sub-chains; every time
- * below 2^36 ns (PAAM_E_RANGE otherwise). */
+ * below 2^36 ns; and the analysis keeps per-set tables of
+ * 8*(4C + 2*NA*C + 2*X*C + 2*NA) + 4*(2C + NA*C + 10X + 16) bytes in the
+ * 160 KB of LDS of a compute unit (plus 8*X*C when X*C <= 512), so for
+ * example at most 869 chains with 8 executors and one accelerator, or 2,154
+ * chains with one executor (C chains, X executors, NA accelerators).
+ * PAAM_E_RANGE otherwise, at upload (and from paam_chainset_bytes). */
 paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, size_t arena_bytes,
                                  paam_stream stream, paam_chainset **out);
 void paam_chainset_free(paam_chainset *cs);
@@ -103,7 +108,8 @@ typedef struct {
   int32_t util_permille; /* >= 0: every E and A enters as floor(x * util_permille / 1000) */
   int32_t full;          /* 1: every chain's bound; 0: verdict only, stop a set at its first miss */
   int32_t bound;         /* PAAM_BOUND_* */
-  int32_t waves_per_cu;  /* persistent waves per compute unit; 0 = tuned default */
+  int32_t waves_per_cu;  /* persistent waves per compute unit; 0 = per size class, the
+                            choice of paam_wcrt_autotune if it ran on the handle, else 8 */
 } paam_wcrt_opts;
 
 /* Workspace for paam_wcrt_batch (device, caller-owned, 256-B aligned). */
@@ -135,16 +141,30 @@ paam_status paam_wcrt_batch_noalloc(const paam_chainset *cs, const paam_wcrt_opt
                                     int8_t *set_sched, int32_t *set_worst, int64_t *set_worst_R,
                                     int64_t *chain_R, paam_stream stream);
 
-/* Schedule autotuner: runs paam_wcrt_batch on this batch with o->waves_per_cu
- * set to each of the n_cand values in cand (1..32), reps times each, timed
- * with HIP events on the stream, and writes the fastest value into
- * o->waves_per_cu and its mean time per launch (ms) into *best_ms.  Outputs
- * and workspace as for paam_wcrt_batch; the workspace must hold the largest
- * candidate's paam_wcrt_bytes.  Blocks until the timing runs have finished. */
-paam_status paam_wcrt_autotune(const paam_chainset *cs, paam_wcrt_opts *o, const int32_t *cand,
+/* Schedule autotuner.  For each size class of the batch (sets grouped by
+ * chain count: up to 16, 32, 64, ... chains; the analysis launches once per
+ * class), times the class's launch with every pair of persistent waves per
+ * compute unit from cand (n_cand values in 1..32) and evaluations of each
+ * lane's recurrence per engine step (1, 2, 3): one untimed launch, then reps
+ * timed ones with HIP events on the stream.  The fastest pair of each class
+ * is stored in the handle (the only change a call makes to a handle: do not
+ * run it concurrently with other calls on the same handle); o->waves_per_cu
+ * is set to 0, which makes later calls use the stored per-class choices, and
+ * *best_ms receives the sum of the classes' best times (one batch launch).
+ * Outputs as for paam_wcrt_batch (overwritten); the workspace must hold
+ * paam_wcrt_bytes for waves_per_cu = the largest candidate.  Query the
+ * workspace size again after tuning.  Blocks until the timing has finished. */
+paam_status paam_wcrt_autotune(paam_chainset *cs, paam_wcrt_opts *o, const int32_t *cand,
                                int32_t n_cand, int32_t reps, int8_t *set_sched,
                                int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R,
                                void *d_ws, size_t ws_bytes, paam_stream stream, float *best_ms);
+
+/* The schedule of the batch's size classes: for class k < cap,
+ * classes[4k .. 4k+3] = largest chain count, number of sets, waves per CU and
+ * evaluations per engine step used when o->waves_per_cu is 0 (the
+ * autotuner's choice, else 8 and 2).  *n_classes receives the class count. */
+paam_status paam_wcrt_schedule(const paam_chainset *cs, int32_t *classes, int32_t cap,
+                               int32_t *n_classes);
 
 /* ---------------- priority-order search (candidate orders) ----------------
  * Candidate 0 of a set is its uploaded order (chains by decreasing prio).

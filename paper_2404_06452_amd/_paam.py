@@ -23,6 +23,7 @@ PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
 EXPORTED = (
     "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
     "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_batch_noalloc", "paam_wcrt_autotune",
+    "paam_wcrt_schedule",
     "paam_search_bytes",
     "paam_priority_search", "paam_candidate_bytes", "paam_candidate_wcrt", "paam_features_bytes", "paam_features",
     "paam_mlp_pack", "paam_mlp_forward", "paam_mlp_backward_bytes", "paam_mlp_backward",
@@ -81,6 +82,8 @@ def lib():
                                           ctypes.c_int32, P, P, P, P, P, S, P,
                                           ctypes.POINTER(ctypes.c_float)]
         L.paam_wcrt_autotune.restype = ctypes.c_int32
+        L.paam_wcrt_schedule.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.paam_wcrt_schedule.restype = ctypes.c_int32
         L.paam_search_bytes.argtypes = [P, ctypes.POINTER(paam_search_opts), ctypes.POINTER(S)]
         L.paam_priority_search.argtypes = [P, ctypes.POINTER(paam_search_opts), P, P, P, P, S, P]
         I64, I32, U64, F = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_float
@@ -235,6 +238,16 @@ def paam_wcrt_autotune(cs: Chainset, opts: paam_wcrt_opts, candidates, reps: int
                                    ctypes.byref(best)),
           "paam_wcrt_autotune")
     return float(best.value)
+
+
+def paam_wcrt_schedule(cs: Chainset) -> list:
+    """Per size class: (largest chain count, sets, waves per CU, evaluations
+    per engine step) used when waves_per_cu is 0."""
+    buf = np.zeros((16, 4), np.int32)
+    n = ctypes.c_int32(0)
+    check(lib().paam_wcrt_schedule(cs.handle, buf.ctypes.data, 16, ctypes.byref(n)),
+          "paam_wcrt_schedule")
+    return [tuple(int(v) for v in buf[k]) for k in range(min(n.value, 16))]
 
 
 def workspace(nbytes: int, device="cuda:0"):

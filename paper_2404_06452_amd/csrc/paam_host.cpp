@@ -364,7 +364,7 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     const int64_t s = P.work_order[i];
     const int k = size_class(s);
     if (P.classes.empty() || size_class(P.work_order[P.classes.back().begin]) != k)
-      P.classes.push_back(paam::SizeClass{i, 0, 0, 0, 0, 1, 1});
+      P.classes.push_back(paam::SizeClass{i, 0, 0, 0, 0, 1, 1, 0, 0});
     paam::SizeClass &c = P.classes.back();
     const int64_t c0 = h->set_chain_off[s];
     const int C = (int)(h->set_chain_off[s + 1] - c0);
@@ -375,6 +375,21 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     c.max_NA = std::max(c.max_NA, (int32_t)(h->set_accel_off[s + 1] - h->set_accel_off[s]));
     c.max_runs = std::max(c.max_runs, nrun[s]);
     c.max_segs = std::max(c.max_segs, (int32_t)(h->cb_seg_off[cb1] - h->cb_seg_off[cb0]));
+  }
+  // the per-wave LDS tables of each class (the search and candidate kernels,
+  // whose layout is the larger) must fit the 160 KB of a compute unit
+  for (const paam::SizeClass &c : P.classes) {
+    paam::DevBatch b{};
+    b.max_C = c.max_C;
+    b.max_X = c.max_X;
+    b.max_NA = c.max_NA;
+    b.max_runs = c.max_runs;
+    b.max_segs = c.max_segs;
+    const size_t lds = std::max(paam::wave_lds_bytes(b), paam::wcrt_lds_bytes(b));
+    RNG(lds <= 160 * 1024,
+        "sets of %d chains, %d executors and %d accelerators need %zu bytes of LDS per wave "
+        "(max 163840): fewer chains or executors per set",
+        c.max_C, c.max_X, c.max_NA, lds);
   }
   return PAAM_OK;
 }
@@ -626,6 +641,25 @@ static int grid_n(int64_t n_sets, const paam_wcrt_opts *o) {
   return (int)std::max<int64_t>(g, 1);
 }
 
+constexpr int kDefaultMicro = 2;
+
+// Schedule of size class k: waves per CU (o->waves_per_cu if set, else the
+// autotuner's choice for the class, else 8) and evaluations per engine step.
+static void class_schedule(const paam_chainset *cs, int k, const paam_wcrt_opts *o, int *waves,
+                           int *micro) {
+  const paam::SizeClass &c = cs->cls[k];
+  *waves = o->waves_per_cu > 0 ? o->waves_per_cu : (c.tuned_waves > 0 ? c.tuned_waves : 8);
+  *micro = c.tuned_micro > 0 ? c.tuned_micro : kDefaultMicro;
+}
+
+static int class_grid(const paam_chainset *cs, int k, const paam_wcrt_opts *o) {
+  int w = 0, m = 0;
+  class_schedule(cs, k, o, &w, &m);
+  paam_wcrt_opts t = *o;
+  t.waves_per_cu = w;
+  return grid_n(cs->cls[k].count, &t);
+}
+
 paam_status paam_wcrt_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, size_t *ws_bytes) {
   if (!cs || !ws_bytes) return fail(PAAM_E_INVAL, "null argument");
   paam_status st = check_opts(o);
@@ -633,46 +667,70 @@ paam_status paam_wcrt_bytes(const paam_chainset *cs, const paam_wcrt_opts *o, si
   size_t need = 256;
   for (int k = 0; k < cs->n_classes; ++k) {
     const paam::DevBatch b = class_view(cs, k);
-    need = std::max(need, 256 + (size_t)grid_n(b.n_sets, o) * paam::wcrt_scratch_bytes(b));
+    need = std::max(need, 256 + (size_t)class_grid(cs, k, o) * paam::wcrt_scratch_bytes(b));
   }
   *ws_bytes = need;
   return PAAM_OK;
 }
 
-paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, int8_t *set_sched,
-                            int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R, void *d_ws,
-                            size_t ws_bytes, paam_stream stream) {
+// Launches the analysis of size class k with the given schedule.
+static paam_status launch_class(const paam_chainset *cs, int k, const paam_wcrt_opts *o,
+                                int waves, int micro, int8_t *set_sched, int32_t *set_worst,
+                                int64_t *set_worst_R, int64_t *chain_R, unsigned char *base,
+                                int64_t max_grid, paam_stream stream) {
+  paam::WcrtLaunch L;
+  L.b = class_view(cs, k);
+  L.o = *o;
+  L.set_sched = set_sched;
+  L.set_worst = set_worst;
+  L.set_worst_R = set_worst_R;
+  L.chain_R = o->full ? chain_R : nullptr;
+  L.counter = reinterpret_cast<unsigned long long *>(base);  // zeroed by a kernel per launch
+  L.scratch = base + 256;
+  L.scratch_stride = paam::wcrt_scratch_bytes(L.b);
+  L.lds_bytes = paam::wcrt_lds_bytes(L.b);
+  paam_wcrt_opts t = *o;
+  t.waves_per_cu = waves;
+  L.grid = (int)std::min<int64_t>(grid_n(L.b.n_sets, &t), max_grid);
+  L.micro = micro;
+  int e = paam::launch_wcrt(L, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
+  return PAAM_OK;
+}
+
+static paam_status check_batch_args(const paam_chainset *cs, const paam_wcrt_opts *o,
+                                    int8_t *set_sched, int32_t *set_worst, int64_t *set_worst_R,
+                                    int64_t *chain_R) {
   if (!cs) return fail(PAAM_E_INVAL, "chainset is null");
   paam_status st = check_opts(o);
   if (st != PAAM_OK) return st;
   if (!set_sched || !set_worst || !set_worst_R)
     return fail(PAAM_E_INVAL, "set outputs must not be null");
   if (o->full && !chain_R) return fail(PAAM_E_INVAL, "full mode needs chain_R");
+  if (paam::wcrt_lds_bytes(cs->dev) > 160 * 1024)
+    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
+                paam::wcrt_lds_bytes(cs->dev));
+  return PAAM_OK;
+}
+
+paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, int8_t *set_sched,
+                            int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R, void *d_ws,
+                            size_t ws_bytes, paam_stream stream) {
+  paam_status st = check_batch_args(cs, o, set_sched, set_worst, set_worst_R, chain_R);
+  if (st != PAAM_OK) return st;
   size_t need = 0;
   paam_wcrt_bytes(cs, o, &need);
   if (!d_ws || ws_bytes < need)
     return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
   if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
     return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
-  if (paam::wcrt_lds_bytes(cs->dev) > 160 * 1024)
-    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
-                paam::wcrt_lds_bytes(cs->dev));
   // one launch per size class, in stream order on the same workspace
   for (int k = 0; k < cs->n_classes; ++k) {
-    paam::WcrtLaunch L;
-    L.b = class_view(cs, k);
-    L.o = *o;
-    L.set_sched = set_sched;
-    L.set_worst = set_worst;
-    L.set_worst_R = set_worst_R;
-    L.chain_R = o->full ? chain_R : nullptr;
-    L.counter = static_cast<unsigned long long *>(d_ws);
-    L.scratch = static_cast<unsigned char *>(d_ws) + 256;
-    L.scratch_stride = paam::wcrt_scratch_bytes(L.b);
-    L.lds_bytes = paam::wcrt_lds_bytes(L.b);
-    L.grid = grid_n(L.b.n_sets, o);
-    int e = paam::launch_wcrt(L, stream);
-    if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
+    int w = 0, m = 0;
+    class_schedule(cs, k, o, &w, &m);
+    st = launch_class(cs, k, o, w, m, set_sched, set_worst, set_worst_R, chain_R,
+                      static_cast<unsigned char *>(d_ws), INT64_MAX, stream);
+    if (st != PAAM_OK) return st;
   }
   return PAAM_OK;
 }
@@ -680,15 +738,8 @@ paam_status paam_wcrt_batch(const paam_chainset *cs, const paam_wcrt_opts *o, in
 paam_status paam_wcrt_batch_noalloc(const paam_chainset *cs, const paam_wcrt_opts *o,
                                     int8_t *set_sched, int32_t *set_worst, int64_t *set_worst_R,
                                     int64_t *chain_R, paam_stream stream) {
-  if (!cs) return fail(PAAM_E_INVAL, "chainset is null");
-  paam_status st = check_opts(o);
+  paam_status st = check_batch_args(cs, o, set_sched, set_worst, set_worst_R, chain_R);
   if (st != PAAM_OK) return st;
-  if (!set_sched || !set_worst || !set_worst_R)
-    return fail(PAAM_E_INVAL, "set outputs must not be null");
-  if (o->full && !chain_R) return fail(PAAM_E_INVAL, "full mode needs chain_R");
-  if (paam::wcrt_lds_bytes(cs->dev) > 160 * 1024)
-    return fail(PAAM_E_RANGE, "sets need %zu bytes of LDS per wave (max 163840)",
-                paam::wcrt_lds_bytes(cs->dev));
   // every size class must fit at least one wave into the static scratch
   for (int k = 0; k < cs->n_classes; ++k) {
     const size_t per = paam::wcrt_scratch_bytes(class_view(cs, k));
@@ -701,28 +752,19 @@ paam_status paam_wcrt_batch_noalloc(const paam_chainset *cs, const paam_wcrt_opt
   void *base = nullptr;
   const int he = paam::noalloc_scratch(&base);
   if (he != 0) return hip_fail((hipError_t)he, "hipGetSymbolAddress(scratch)");
-  unsigned char *sbase = static_cast<unsigned char *>(base);
   for (int k = 0; k < cs->n_classes; ++k) {
-    paam::WcrtLaunch L;
-    L.b = class_view(cs, k);
-    L.o = *o;
-    L.set_sched = set_sched;
-    L.set_worst = set_worst;
-    L.set_worst_R = set_worst_R;
-    L.chain_R = o->full ? chain_R : nullptr;
-    L.counter = reinterpret_cast<unsigned long long *>(sbase);  // zeroed by a kernel per launch
-    L.scratch = sbase + 256;
-    L.scratch_stride = paam::wcrt_scratch_bytes(L.b);
-    L.lds_bytes = paam::wcrt_lds_bytes(L.b);
-    const int64_t fit = (int64_t)((paam::kNoAllocScratchBytes - 256) / L.scratch_stride);
-    L.grid = (int)std::min<int64_t>(grid_n(L.b.n_sets, o), fit);
-    int e = paam::launch_wcrt(L, stream);
-    if (e != 0) return hip_fail((hipError_t)e, "wcrt launch");
+    int w = 0, m = 0;
+    class_schedule(cs, k, o, &w, &m);
+    const int64_t fit = (int64_t)((paam::kNoAllocScratchBytes - 256) /
+                                  paam::wcrt_scratch_bytes(class_view(cs, k)));
+    st = launch_class(cs, k, o, w, m, set_sched, set_worst, set_worst_R, chain_R,
+                      static_cast<unsigned char *>(base), fit, stream);
+    if (st != PAAM_OK) return st;
   }
   return PAAM_OK;
 }
 
-paam_status paam_wcrt_autotune(const paam_chainset *cs, paam_wcrt_opts *o, const int32_t *cand,
+paam_status paam_wcrt_autotune(paam_chainset *cs, paam_wcrt_opts *o, const int32_t *cand,
                                int32_t n_cand, int32_t reps, int8_t *set_sched,
                                int32_t *set_worst, int64_t *set_worst_R, int64_t *chain_R,
                                void *d_ws, size_t ws_bytes, paam_stream stream, float *best_ms) {
@@ -731,7 +773,20 @@ paam_status paam_wcrt_autotune(const paam_chainset *cs, paam_wcrt_opts *o, const
     return fail(PAAM_E_INVAL, "need 1 <= n_cand <= 64 and 1 <= reps <= 100");
   for (int i = 0; i < n_cand; ++i)
     if (cand[i] < 1 || cand[i] > 32) return fail(PAAM_E_INVAL, "candidate waves_per_cu outside 1..32");
-  hipStream_t st = (hipStream_t)stream;
+  paam_status st = check_batch_args(cs, o, set_sched, set_worst, set_worst_R, chain_R);
+  if (st != PAAM_OK) return st;
+  // the workspace must hold the largest candidate's grid for every class
+  int wmax = 0;
+  for (int i = 0; i < n_cand; ++i) wmax = std::max(wmax, (int)cand[i]);
+  paam_wcrt_opts tmax = *o;
+  tmax.waves_per_cu = wmax;
+  size_t need = 0;
+  paam_wcrt_bytes(cs, &tmax, &need);
+  if (!d_ws || ws_bytes < need)
+    return fail(PAAM_E_NOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
+    return fail(PAAM_E_INVAL, "workspace is not 256-byte aligned");
+  hipStream_t sh = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
@@ -739,37 +794,63 @@ paam_status paam_wcrt_autotune(const paam_chainset *cs, paam_wcrt_opts *o, const
     if (e0) (void)hipEventDestroy(e0);
     return hip_fail(he, "hipEventCreate");
   }
+  unsigned char *base = static_cast<unsigned char *>(d_ws);
   paam_status st_out = PAAM_OK;
-  float best = 0.0f;
-  int32_t best_w = -1;
-  paam_wcrt_opts t = *o;
-  for (int i = 0; i < n_cand && st_out == PAAM_OK; ++i) {
-    t.waves_per_cu = cand[i];
-    // one untimed launch, then reps timed ones
-    st_out = paam_wcrt_batch(cs, &t, set_sched, set_worst, set_worst_R, chain_R, d_ws, ws_bytes,
-                             stream);
-    if (st_out != PAAM_OK) break;
-    he = hipEventRecord(e0, st);
-    for (int r = 0; r < reps && st_out == PAAM_OK && he == hipSuccess; ++r)
-      st_out = paam_wcrt_batch(cs, &t, set_sched, set_worst, set_worst_R, chain_R, d_ws, ws_bytes,
-                               stream);
-    if (he == hipSuccess) he = hipEventRecord(e1, st);
-    if (he == hipSuccess) he = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-    if (he != hipSuccess && st_out == PAAM_OK) st_out = hip_fail(he, "autotune timing");
-    if (st_out != PAAM_OK) break;
-    ms /= (float)reps;
-    if (best_w < 0 || ms < best) {
-      best = ms;
-      best_w = cand[i];
+  float total = 0.0f;
+  // per size class: every (waves per CU, evaluations per step) pair, one
+  // untimed launch then reps timed ones; the fastest is kept in the handle
+  for (int k = 0; k < cs->n_classes && st_out == PAAM_OK; ++k) {
+    float best = 0.0f;
+    int bw = -1, bm = kDefaultMicro;
+    for (int i = 0; i < n_cand && st_out == PAAM_OK; ++i)
+      for (int m = 1; m <= 3 && st_out == PAAM_OK; ++m) {
+        st_out = launch_class(cs, k, o, cand[i], m, set_sched, set_worst, set_worst_R, chain_R,
+                              base, INT64_MAX, stream);
+        if (st_out != PAAM_OK) break;
+        he = hipEventRecord(e0, sh);
+        for (int r = 0; r < reps && st_out == PAAM_OK && he == hipSuccess; ++r)
+          st_out = launch_class(cs, k, o, cand[i], m, set_sched, set_worst, set_worst_R,
+                                chain_R, base, INT64_MAX, stream);
+        if (he == hipSuccess) he = hipEventRecord(e1, sh);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess && st_out == PAAM_OK) st_out = hip_fail(he, "autotune timing");
+        if (st_out != PAAM_OK) break;
+        ms /= (float)reps;
+        if (bw < 0 || ms < best) {
+          best = ms;
+          bw = cand[i];
+          bm = m;
+        }
+      }
+    if (st_out == PAAM_OK) {
+      cs->cls[k].tuned_waves = bw;
+      cs->cls[k].tuned_micro = bm;
+      total += best;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st_out != PAAM_OK) return st_out;
-  o->waves_per_cu = best_w;
-  *best_ms = best;
+  o->waves_per_cu = 0;  // use the per-class choices
+  *best_ms = total;
+  return PAAM_OK;
+}
+
+paam_status paam_wcrt_schedule(const paam_chainset *cs, int32_t *classes, int32_t cap,
+                               int32_t *n_classes) {
+  if (!cs || !n_classes || (cap > 0 && !classes)) return fail(PAAM_E_INVAL, "null argument");
+  *n_classes = cs->n_classes;
+  for (int k = 0; k < cs->n_classes && k < cap; ++k) {
+    int w = 0, m = 0;
+    paam_wcrt_opts o{};
+    class_schedule(cs, k, &o, &w, &m);
+    classes[4 * k] = cs->cls[k].max_C;
+    classes[4 * k + 1] = (int32_t)std::min<int64_t>(cs->cls[k].count, INT32_MAX);
+    classes[4 * k + 2] = w;
+    classes[4 * k + 3] = m;
+  }
   return PAAM_OK;
 }
 

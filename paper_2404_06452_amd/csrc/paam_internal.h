@@ -77,6 +77,8 @@ namespace paam {
 struct SizeClass {
   int64_t begin, count;
   int32_t max_C, max_X, max_NA, max_runs, max_segs;
+  // schedule of the analysis kernel chosen by paam_wcrt_autotune (0: not tuned)
+  int32_t tuned_waves, tuned_micro;
 };
 constexpr int kMaxClasses = 12;
 }  // namespace paam
@@ -104,6 +106,7 @@ struct WcrtLaunch {
   size_t scratch_stride;        // bytes per wave
   size_t lds_bytes;
   int grid;
+  int micro;                    // evaluations of each lane's recurrence per engine step
 };
 
 struct SearchLaunch {

@@ -170,9 +170,6 @@ __device__ Scratch carve_scratch(unsigned char *base, int max_segs, int max_runs
 // reports set_sched = -1.
 constexpr int kMaxIter = 1 << 20;
 
-// Evaluations of each lane's recurrence per engine step of the queue-driven
-// analysis: the refill and dependency bookkeeping of a step is shared by them.
-constexpr int kMicro = 2;
 
 // Packed word of a sub-chain: rank of its chain in bits 0-11 (fewer than
 // 4,096 chains per set), executor in bits 12-16, accelerator mask in bits
@@ -815,7 +812,7 @@ __device__ __forceinline__ double pack2(int hi, int lo) { return __hiloint2doubl
 template <class KR, bool kSbLds>
 __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_t set, KR kr,
                               Lds &L, Scratch &S, int8_t *set_sched, int32_t *set_worst,
-                              int64_t *set_worst_R, int64_t *chain_R) {
+                              int64_t *set_worst_R, int64_t *chain_R, int micro) {
   const int lane = threadIdx.x;
   const int64_t c0 = b.set_chain_off[set];
   const int C = (int)(b.set_chain_off[set + 1] - c0);
@@ -950,7 +947,8 @@ __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_
 
   // ---- Lemma 2 / Eq. (3): one segment per lane, refilled from the queue
   //      (the next 64 queue records are loaded one step ahead); a step
-  //      iterates every lane's recurrence up to kMicro times ----
+  //      iterates every lane's recurrence up to `micro` times, sharing the
+  //      step's refill and bookkeeping ----
   {
     int qnext = 0;
     bool have = false;
@@ -983,7 +981,7 @@ __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_
       const int klo = min(wave_umin(have ? rho : C), hend);
       const double *ah = L.Ahat + a * C;
       bool done = false;
-      for (int it = 0; it < kMicro; ++it) {
+      for (int it = 0; it < micro; ++it) {
         double n0 = 0.0, n1 = 0.0;
         int k2 = 0;
 #pragma unroll 2
@@ -1077,9 +1075,11 @@ __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_
     atomicAdd(&L.WP[e * C + rho], E + hs0);
     atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
     S.cst[s] = E + (needL3 ? 0.0 : hs0);
-    S.L2[s] = L2;
-    S.A0[s] = A0;
-    S.eps[s] = eps;
+    if (needL3) {  // the Lemma 3 constants are read by these sub-chains only
+      S.L2[s] = L2;
+      S.A0[s] = A0;
+      S.eps[s] = eps;
+    }
     S.info[s] = rho | (e << kExecShift) | (accm << kAccShift) | (needL3 ? kNeedL3 : 0) |
                 (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
   }
@@ -1264,10 +1264,10 @@ __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_
         e_mid = rhi + 1 < hend ? rhi + 1 : hend;
         anyl3 = wave_any(l3on);
       }
-      // up to kMicro evaluations with this step's items and weights
+      // up to `micro` evaluations with this step's items and weights
       double rr = r, hh = hs;
       bool conv = false;
-      for (int it = 0; it < kMicro; ++it) {
+      for (int it = 0; it < micro; ++it) {
         double I0 = 0.0, I1 = 0.0, l3 = 0.0;
         int h = 0;
         if (NA == 1) {
@@ -1490,7 +1490,7 @@ __global__ __launch_bounds__(kWave, 5) void wcrt_kernel(WcrtLaunch L) {
     const int64_t c0 = L.b.set_chain_off[set];
     KRConst kr{(const __attribute__((address_space(4))) double *)(L.b.KRr + 2 * c0)};
     analyse_set_q<KRConst, false>(L.b, L.o, set, kr, l, s, L.set_sched, L.set_worst,
-                                   L.set_worst_R, L.chain_R);
+                                   L.set_worst_R, L.chain_R, L.micro);
   }
 }
 

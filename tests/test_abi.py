@@ -115,3 +115,17 @@ def test_missing_library_fails_loudly(tmp_path):
             _paam.Chainset(chaingen.generate("small", 2), device="cpu")
     finally:
         _paam._lib, _paam.LIBPAAM = saved
+
+
+def test_upload_rejects_sets_whose_tables_exceed_lds():
+    """A set of 870 chains on 8 executors needs more than the 160 KB of LDS
+    of a compute unit for its analysis tables: rejected by the size query
+    (the upload validates the same way), 869 chains are accepted."""
+    from paper_2404_06452_amd import _paam, chaingen
+    from paper_2404_06452_amd.chaingen import GenParams
+    n = ctypes.c_size_t(0)
+    for C, rc in ((869, 0), (870, -2)):
+        p = GenParams(7, (C, C), (1, 1), 8, (0.5, 0.5), (0.5, 0.5), (0.1, 0.5))
+        hb = _paam.HostBatch(chaingen.generate(p, 1))
+        assert _paam.lib().paam_chainset_bytes(ctypes.byref(hb.struct), ctypes.byref(n)) == rc, C
+    assert b"LDS" in _paam.lib().paam_last_error()

@@ -175,7 +175,16 @@ def test_autotune_picks_a_candidate_and_keeps_results():
     ws = _paam.workspace(_paam.paam_wcrt_bytes(dev, _paam.wcrt_opts(full=True, waves_per_cu=8)))
     ms = _paam.paam_wcrt_autotune(dev, o, [2, 4, 8], 2, out, ws)
     torch.cuda.synchronize()
-    assert o.waves_per_cu in (2, 4, 8) and ms > 0
+    assert o.waves_per_cu == 0 and ms > 0
+    sched = _paam.paam_wcrt_schedule(dev)
+    assert len(sched) >= 2 and sum(n for _, n, _, _ in sched) == cs.n_sets
+    assert all(w in (2, 4, 8) and m in (1, 2, 3) for _, _, w, m in sched), sched
     r = oracle.wcrt(cs, full=True, util_permille=300)
     assert np.array_equal(out.chain_R.cpu().numpy()[:cs.n_chains], r["chain_R"])
     assert np.array_equal(out.set_sched.cpu().numpy(), r["sched"])
+    # later calls with waves_per_cu = 0 run the tuned per-class schedule
+    ws2 = _paam.workspace(_paam.paam_wcrt_bytes(dev, o))
+    out.chain_R.fill_(-1)
+    _paam.paam_wcrt_batch(dev, o, out, ws2)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.chain_R.cpu().numpy()[:cs.n_chains], r["chain_R"])
