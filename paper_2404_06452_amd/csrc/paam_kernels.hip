@@ -1135,60 +1135,94 @@ __device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_
   for (int i = lane; i < X * C; i += kWave)
     if (L.hpx[i / C] == 0) L.Pt[i] = 0.0;
 
-  // ---- the queue of sub-chains: the Lemma 3 sub-chains first (by the number
-  //      of higher-priority executors on their core, then rank), then those
-  //      that read none of them (increasing rank), then the others (decreasing
-  //      rank, written from the back); records (constant part of the
-  //      recurrence, s | packed word) ----
+  __syncthreads();
+
+  // ---- verdict mode: the first iterate of every sub-chain (each interferer
+  //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
+  //      a chain whose sum of them passes its deadline proves the miss ----
+  bool missed = false;
+  if (!full) {
+    for (int s = lane; s < nrun; s += kWave) {
+      const int w = S.info[s];
+      const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
+      const double *wp = L.WP + e * C, *pt = L.Pt + e * C;
+      double lb = S.cst[s];
+      for (int h = 0; h < rho; ++h) lb += wp[h];
+      if (w & kHasP)
+        for (int h = rho + 1; h < C; ++h) lb += pt[h];
+      atomicAdd(&L.partial[rho], lb);
+    }
+    __syncthreads();
+    bool miss = false;
+    for (int rho = lane; rho < C; rho += kWave) {
+      if (L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho]) miss = true;
+      L.partial[rho] = 0.0;
+    }
+    missed = wave_any(miss);
+    __syncthreads();
+  }
+
+  // ---- the queue of sub-chains: the Lemma 3 sub-chains first, each after
+  //      every one it reads (by the number of higher-priority executors on
+  //      their core, then rank), then those that read none of them
+  //      (increasing position), then the others (decreasing position, written
+  //      from the back); records (constant part of the recurrence,
+  //      s | packed word) ----
   int n3 = 0;
   for (int l = 0; l <= maxlev; ++l) n3 += L.dmin[l];
-  if (lane == 0) {
-    int o = 0;
-    for (int l = 0; l <= maxlev; ++l) {
-      const int c = L.dmin[l];
-      L.dspin[l] = o;  // running position of level l
-      o += c;
-    }
-  }
-  wave_sync();
-  {
-    int nind = 0, ndep = 0;
+  if (!missed) {
+    int nl3 = 0, nind = 0, ndep = 0;
     for (int sb = 0; sb < nrun; sb += kWave) {
       const int s = sb + lane;
-      int w = 0, cat = -1;  // level of a Lemma 3 sub-chain; maxlev+1 independent; maxlev+2 other
+      int w = 0, cat = -1;  // 0: Lemma 3; 1: reads none of them; 2: other
       double c = 0.0;
       if (s < nrun) {
         w = S.info[s];
         c = S.cst[s];
         const int e = (w >> kExecShift) & 31;
-        if (w & kNeedL3) cat = __popc((uint32_t)L.hpx[e]);
-        else cat = ((w & kRankMask) <= L.dfirst[e] && !L.dblk[e]) ? maxlev + 1 : maxlev + 2;
+        if (w & kNeedL3) cat = 0;
+        else cat = ((w & kRankMask) <= L.dfirst[e] && !L.dblk[e]) ? 1 : 2;
       }
       const double2 rec = make_double2(c, pack2(s, w));
-      for (int l = 0; l <= maxlev; ++l) {
-        const unsigned long long m = __ballot(cat == l);
-        if (m) {
-          const int base = L.dspin[l];
-          if (cat == l) S.qr[base + (int)__popcll(m & lanes_below())] = rec;
-          wave_sync();
-          if (lane == 0) L.dspin[l] = base + (int)__popcll(m);
-          wave_sync();
-        }
+      const unsigned long long m3 = __ballot(cat == 0);
+      const unsigned long long mi = __ballot(cat == 1);
+      const unsigned long long md = __ballot(cat == 2);
+      if (cat == 0) {
+        // unsorted, into the free Lemma 2 queue (a Lemma 3 sub-chain has a
+        // segment of its own, so there are at most as many as segments)
+        const int i = nl3 + (int)__popcll(m3 & lanes_below());
+        S.qs[i] = rec;
+        S.alist[i] = (__popc((uint32_t)L.hpx[(w >> kExecShift) & 31]) << 12) | (w & kRankMask);
       }
-      const unsigned long long mi = __ballot(cat == maxlev + 1);
-      const unsigned long long md = __ballot(cat == maxlev + 2);
-      if (cat == maxlev + 1) S.qr[n3 + nind + (int)__popcll(mi & lanes_below())] = rec;
-      if (cat == maxlev + 2) S.qr[nrun - 1 - (ndep + (int)__popcll(md & lanes_below()))] = rec;
+      if (cat == 1) S.qr[n3 + nind + (int)__popcll(mi & lanes_below())] = rec;
+      if (cat == 2) S.qr[nrun - 1 - (ndep + (int)__popcll(md & lanes_below()))] = rec;
+      nl3 += (int)__popcll(m3);
       nind += (int)__popcll(mi);
       ndep += (int)__popcll(md);
+    }
+    __syncthreads();
+    // the Lemma 3 sub-chains in key order (ties by position): each one's
+    // place is the number of keys before it
+    for (int ib = 0; ib < n3; ib += kWave) {
+      const int i = ib + lane;
+      const int ki = i < n3 ? S.alist[i] : 0x7fffffff;
+      int pos = 0;
+      for (int jb = 0; jb < n3; jb += kWave) {
+        const int kv = jb + lane < n3 ? S.alist[jb + lane] : 0x7fffffff;
+        const int jn = min(kWave, n3 - jb);
+        for (int jj = 0; jj < jn; ++jj) {
+          const int kj = __builtin_amdgcn_readlane(kv, jj);
+          pos += (kj < ki || (kj == ki && jb + jj < i)) ? 1 : 0;
+        }
+      }
+      if (i < n3) S.qr[pos] = S.qs[i];
     }
   }
   __syncthreads();
 
   // ---- Theorem 1 / Eq. (6): one sub-chain per lane, refilled from the
   //      queue; the next 64 records are loaded one step ahead ----
-  bool missed = false;
-  {
+  if (!missed) {
     int qnext = 0;
     bool have = false;
     int s = 0, rho = 0, e = 0, inf1 = 0, hpxm = 0;
