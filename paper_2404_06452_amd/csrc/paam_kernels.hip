@@ -1607,9 +1607,11 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
   o.full = 0;
   const int n_cand = L.o.n_cand;
   for (;;) {
+    // lane 0 claims the next set; the index is then held in scalar registers,
+    // so every branch on it is uniform across the wave
     unsigned long long i = 0;
     if (threadIdx.x == 0) i = atomicAdd(L.counter, 1ull);
-    i = __shfl(i, 0);
+    i = uniform_u64(i);
     if (i >= (unsigned long long)L.b.n_sets) break;
     const int64_t set = L.b.work_order[i];
     const int64_t c0 = L.b.set_chain_off[set];
