@@ -68,7 +68,19 @@ typedef struct {
   const int64_t *accel_eps;     /* [n_accels] per-request server overhead epsilon */
   const int64_t *accel_kappa;   /* [n_accels] device preemption cost kappa */
   const int64_t *eps_hop;       /* [n_sets] communication cost between consecutive sub-chains */
+  /* Several units of one accelerator type (Sec. IV-E, "Managing Multiple
+   * Accelerators"): NULL, or [n_accels] units of each accelerator (1..8,
+   * at most 8 units per set in all).  Then accel[] names a type, and every
+   * segment is bound to one unit of its type at upload by worst-fit
+   * decreasing (paam_assign_units); each unit is analysed as an accelerator
+   * of its own with its type's buckets, epsilon and kappa. */
+  const int16_t *accel_units;
+  int32_t unit_group;           /* PAAM_UNITS_*: what the bin packing places as one item */
 } paam_chainset_host;
+
+#define PAAM_UNITS_SEGMENT 0  /* each accelerator segment on its own */
+#define PAAM_UNITS_CALLBACK 1 /* a callback's segments on one type stay together */
+#define PAAM_UNITS_CHAIN 2    /* a chain's segments on one type stay together */
 
 typedef struct paam_chainset paam_chainset; /* opaque host handle of an uploaded batch */
 
@@ -86,11 +98,32 @@ paam_status paam_chainset_bytes(const paam_chainset_host *h, size_t *arena_bytes
  * 8*(4C + 2*NA*C + 2*X*C + 2*NA) + 4*(2C + NA*C + 10X + 16) bytes in the
  * 160 KB of LDS of a compute unit (plus 8*X*C when X*C <= 512), so for
  * example at most 869 chains with 8 executors and one accelerator, or 2,154
- * chains with one executor (C chains, X executors, NA accelerators).
- * PAAM_E_RANGE otherwise, at upload (and from paam_chainset_bytes). */
+ * chains with one executor (C chains, X executors, NA accelerators; with
+ * accel_units, NA counts units).  With accel_units a set holds at most 2048
+ * segments.  PAAM_E_RANGE otherwise, at upload (and from
+ * paam_chainset_bytes). */
 paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, size_t arena_bytes,
                                  paam_stream stream, paam_chainset **out);
 void paam_chainset_free(paam_chainset *cs);
+
+/* Binds every segment of a batch uploaded with accel_units to one unit of its
+ * accelerator type (Sec. IV-E: at registration, by a bin-packing heuristic
+ * such as worst-fit decreasing), on the device, in place; upload runs it
+ * once, and it may run again (the result is the same).  Items: one segment,
+ * or the segments of one callback or one chain on one type (unit_group).
+ * Size of an item: its utilisation sum(A)/T in fixed point,
+ * floor(min(sum(A), 2^36) * 2^26 / T) clamped at 2^36.  Items are placed
+ * largest first (ties: higher chain priority, then lower first segment
+ * index), each on the unit of its type with the least load so far (ties: the
+ * lowest unit); a unit's load is the sum of its items' sizes.  The units of a
+ * set are numbered type by type (the units of type 0 first).  Asynchronous
+ * on the stream; PAAM_E_STATE if the batch has no accel_units. */
+paam_status paam_assign_units(paam_chainset *cs, paam_stream stream);
+
+/* Copies the analysed accelerator (set-local unit) of every segment,
+ * [n_segments] int16, into a caller device buffer.  Without accel_units it
+ * is the input accel[].  Asynchronous on the stream. */
+paam_status paam_chainset_seg_units(const paam_chainset *cs, int16_t *d_unit, paam_stream stream);
 
 /* Counts of an uploaded batch: n_sets, n_chains, n_callbacks, n_segments,
  * n_subchains, and the per-set maxima of chains, sub-chains, segments. */

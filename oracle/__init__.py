@@ -83,8 +83,10 @@ def _load():
         lib.oracle_search_range.argtypes = [ctypes.POINTER(_CS), ctypes.POINTER(_Opts),
                                             ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
                                             ctypes.c_int64, P, P, P]
+        lib.oracle_wfd_range.argtypes = [ctypes.POINTER(_CS), P, ctypes.c_int32, ctypes.c_int64,
+                                         ctypes.c_int64, P]
         for f in ("oracle_analyse_set", "oracle_segment_H", "oracle_wcrt_range",
-                  "oracle_candidate_order", "oracle_search_range"):
+                  "oracle_candidate_order", "oracle_search_range", "oracle_wfd_range"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -280,3 +282,48 @@ def guided_search(cs, n_cand, seed, scores, top_k, fallback=True, blocking=BLOCK
                 found[s] = k if r["sched"] > 0 else -2
                 break
     return {"found": found, "n_eval": n_eval}
+
+
+UNITS_SEGMENT, UNITS_CALLBACK, UNITS_CHAIN = 0, 1, 2
+
+
+def wfd_units(cs, units, group=UNITS_SEGMENT):
+    """Worst-fit-decreasing binding of every segment to a unit of its
+    accelerator type (Sec. IV-E, Managing Multiple Accelerators).
+
+    ``units`` [n_accels]: units of each accelerator type; ``group``: an item
+    is a segment, or a callback's or a chain's segments on one type.  Returns
+    the set-local unit of every segment [n_segments]; the units of a set are
+    numbered type by type."""
+    lib = _load()
+    b = _Bound(cs)
+    u = np.ascontiguousarray(units, dtype=np.int16)
+    out = np.full(int(cs.cb_seg_off[-1]), -1, np.int16)
+    if lib.oracle_wfd_range(ctypes.byref(b.s), u.ctypes.data, int(group), 0, int(cs.n_sets),
+                            out.ctypes.data) != 0:
+        raise ValueError("oracle rejected the unit counts")
+    return out
+
+
+class _Split:
+    pass
+
+
+def split_units(cs, units, seg_unit):
+    """The batch whose accelerators are the units: segment g runs on unit
+    ``seg_unit[g]``; every unit keeps its type's buckets and overheads."""
+    units = np.asarray(units, np.int64)
+    out = _Split()
+    for k in _DTYPES:
+        setattr(out, k, np.asarray(getattr(cs, k)).copy())
+    out.n_sets = int(cs.n_sets)
+    out.accel = np.asarray(seg_unit, np.int16).copy()
+    out.accel_buckets = np.repeat(np.asarray(cs.accel_buckets), units).astype(np.int16)
+    out.accel_eps = np.repeat(np.asarray(cs.accel_eps), units).astype(np.int64)
+    out.accel_kappa = np.repeat(np.asarray(cs.accel_kappa), units).astype(np.int64)
+    per_set = np.add.reduceat(units, np.asarray(cs.set_accel_off[:-1])) if len(units) else \
+        np.zeros(0, np.int64)
+    off = np.asarray(cs.set_accel_off)
+    counts = np.where(off[1:] > off[:-1], per_set[:len(off) - 1] if len(per_set) else 0, 0)
+    out.set_accel_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return out

@@ -564,3 +564,108 @@ int oracle_search_range(const oracle_chainsets *cs, const oracle_opts *opt, int3
   }
   return 0;
 }
+
+/* ---------------- units of one accelerator type (Sec. IV-E) ---------------
+ * When a set has several units of an accelerator type, its segments are bound
+ * to units at registration by a bin-packing heuristic, worst-fit decreasing
+ * (the paper's "Managing Multiple Accelerators").  An item is one segment, or
+ * all segments of one callback or of one chain on one type (group 0, 1, 2).
+ * Item size: its utilisation sum(A)/T in fixed point,
+ * floor(min(sum(A), 2^36) * 2^26 / T), clamped at 2^36.  Items are placed
+ * largest first (equal sizes: the item of the higher-priority chain, then the
+ * one whose first segment comes first); each goes to the unit of its type
+ * with the smallest load so far (ties: the lowest unit), and its load grows
+ * by the item's size. */
+#define WFD_SHIFT 26
+#define WFD_CLAMP ((int64_t)1 << 36)
+
+typedef struct {
+  int64_t sum_A;  /* saturated at WFD_CLAMP */
+  int64_t size;
+  int32_t prio;
+  int64_t first;  /* lowest global segment index of the item */
+  int32_t type;
+  int64_t key;    /* callback or chain (global), or segment */
+  int64_t unit;
+} wfd_item;
+
+static int wfd_cmp(const void *pa, const void *pb) {
+  const wfd_item *a = pa, *b = pb;
+  if (a->size != b->size) return a->size > b->size ? -1 : 1;
+  if (a->prio != b->prio) return a->prio > b->prio ? -1 : 1;
+  return a->first < b->first ? -1 : (a->first > b->first);
+}
+
+int oracle_wfd_range(const oracle_chainsets *cs, const int16_t *units, int32_t group, int64_t lo,
+                     int64_t hi, int16_t *unit) {
+  if (group < 0 || group > 2) return -1;
+  for (int64_t set = lo; set < hi; ++set) {
+    const int64_t c0 = cs->set_chain_off[set], c1 = cs->set_chain_off[set + 1];
+    const int64_t a0 = cs->set_accel_off[set], a1 = cs->set_accel_off[set + 1];
+    const int64_t NA = a1 - a0;
+    int64_t base[64], n_units = 0;
+    if (NA > 64) return -1;
+    for (int64_t a = 0; a < NA; ++a) {
+      if (units[a0 + a] < 1) return -1;
+      base[a] = n_units;
+      n_units += units[a0 + a];
+    }
+    const int64_t g0 = cs->cb_seg_off[cs->chain_cb_off[c0]];
+    const int64_t g1 = cs->cb_seg_off[cs->chain_cb_off[c1]];
+    wfd_item *it = zalloc(sizeof(wfd_item) * (size_t)(g1 - g0));
+    int64_t *item_of = zalloc(sizeof(int64_t) * (size_t)(g1 - g0));
+    int64_t *load = zalloc(sizeof(int64_t) * (size_t)n_units);
+    int64_t n = 0;
+    /* gather the items: a segment joins the item of its (key, type) */
+    for (int64_t c = c0; c < c1; ++c)
+      for (int64_t j = cs->chain_cb_off[c]; j < cs->chain_cb_off[c + 1]; ++j)
+        for (int64_t g = cs->cb_seg_off[j]; g < cs->cb_seg_off[j + 1]; ++g) {
+          const int a = cs->accel[g];
+          if (a < 0 || a >= NA) { free(it); free(item_of); free(load); return -1; }
+          const int64_t key = group == 0 ? g : group == 1 ? j : c;
+          int64_t k = 0;
+          while (k < n && !(it[k].key == key && it[k].type == a)) ++k;
+          if (k == n) {
+            it[n].sum_A = 0;
+            it[n].prio = cs->prio[c];
+            it[n].first = g;
+            it[n].type = a;
+            it[n].key = key;
+            ++n;
+          }
+          it[k].sum_A += cs->A[g];
+          if (it[k].sum_A > WFD_CLAMP) it[k].sum_A = WFD_CLAMP;
+          item_of[g - g0] = k;
+          it[k].size = 0;
+        }
+    /* sizes need T of the item's chain */
+    for (int64_t c = c0; c < c1; ++c)
+      for (int64_t j = cs->chain_cb_off[c]; j < cs->chain_cb_off[c + 1]; ++j)
+        for (int64_t g = cs->cb_seg_off[j]; g < cs->cb_seg_off[j + 1]; ++g) {
+          wfd_item *x = &it[item_of[g - g0]];
+          const int64_t sz = (x->sum_A << WFD_SHIFT) / cs->T[c]; /* sum_A <= 2^36 */
+          x->size = sz > WFD_CLAMP ? WFD_CLAMP : sz;
+        }
+    /* the sort permutes the items; remember each item's place by its first segment */
+    qsort(it, (size_t)n, sizeof(wfd_item), wfd_cmp);
+    for (int64_t i = 0; i < n; ++i) {
+      const int a = it[i].type;
+      int64_t best = base[a];
+      for (int64_t u = base[a] + 1; u < base[a] + units[a0 + a]; ++u)
+        if (load[u] < load[best]) best = u;
+      load[best] += it[i].size;
+      it[i].unit = best;
+    }
+    for (int64_t c = c0; c < c1; ++c)
+      for (int64_t j = cs->chain_cb_off[c]; j < cs->chain_cb_off[c + 1]; ++j)
+        for (int64_t g = cs->cb_seg_off[j]; g < cs->cb_seg_off[j + 1]; ++g) {
+          const int64_t key = group == 0 ? g : group == 1 ? j : c;
+          for (int64_t i = 0; i < n; ++i)
+            if (it[i].key == key && it[i].type == cs->accel[g]) { unit[g] = (int16_t)it[i].unit; break; }
+        }
+    free(it);
+    free(item_of);
+    free(load);
+  }
+  return 0;
+}

@@ -79,4 +79,16 @@ int oracle_search_range(const oracle_chainsets *cs, const oracle_opts *opt, int3
                         uint64_t seed, int64_t lo, int64_t hi, int32_t *found, int32_t *n_eval,
                         int64_t *terms);
 
+/* Worst-fit-decreasing binding of the accelerator segments of sets [lo, hi)
+ * to units (Sec. IV-E, Managing Multiple Accelerators).  units[a] >= 1 is
+ * the unit count of accelerator type a (global type index); the units of a
+ * set are numbered type by type.  An item is one segment (group 0), or the
+ * segments of one callback (1) or one chain (2) on one type.  Item size
+ * floor(min(sum A, 2^36) * 2^26 / T) clamped at 2^36; largest first (ties:
+ * higher chain priority, then earlier first segment); each to the
+ * least-loaded unit of its type (ties: lowest unit).  unit[g] receives the
+ * set-local unit of every segment g.  Returns 0, or -1 on bad input. */
+int oracle_wfd_range(const oracle_chainsets *cs, const int16_t *units, int32_t group, int64_t lo,
+                     int64_t hi, int16_t *unit);
+
 #endif

@@ -22,6 +22,7 @@ PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
 
 EXPORTED = (
     "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
+    "paam_assign_units", "paam_chainset_seg_units",
     "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_batch_noalloc", "paam_wcrt_autotune",
     "paam_wcrt_schedule",
     "paam_search_bytes",
@@ -43,8 +44,10 @@ class paam_chainset_host(ctypes.Structure):
     _fields_ = [("n_sets", ctypes.c_int64)] + [(n, ctypes.c_void_p) for n in (
         "set_chain_off", "set_exec_off", "set_accel_off", "chain_cb_off", "cb_seg_off", "T", "D",
         "prio", "spin", "E", "exec", "A", "accel", "exec_core", "exec_prio", "accel_buckets",
-        "accel_eps", "accel_kappa", "eps_hop")]
+        "accel_eps", "accel_kappa", "eps_hop", "accel_units")] + [("unit_group", ctypes.c_int32)]
 
+
+PAAM_UNITS_SEGMENT, PAAM_UNITS_CALLBACK, PAAM_UNITS_CHAIN = 0, 1, 2
 
 class paam_wcrt_opts(ctypes.Structure):
     _fields_ = [("blocking", ctypes.c_int32), ("cap_mult", ctypes.c_int32),
@@ -75,6 +78,8 @@ def lib():
         L.paam_chainset_free.argtypes = [P]
         L.paam_chainset_free.restype = None
         L.paam_chainset_info.argtypes = [P, P]
+        L.paam_assign_units.argtypes = [P, P]
+        L.paam_chainset_seg_units.argtypes = [P, P, P]
         L.paam_wcrt_bytes.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), ctypes.POINTER(S)]
         L.paam_wcrt_batch.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P, S, P]
         L.paam_wcrt_batch_noalloc.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P]
@@ -110,6 +115,7 @@ def lib():
         L.paam_version.argtypes = []
         L.paam_version.restype = ctypes.c_char_p
         for f in ("paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_info",
+                  "paam_assign_units", "paam_chainset_seg_units",
                   "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_batch_noalloc", "paam_search_bytes",
                   "paam_priority_search"):
             getattr(L, f).restype = ctypes.c_int32
@@ -133,14 +139,20 @@ _HOST_DTYPES = {
 
 
 class HostBatch:
-    """paam_chainset_host over contiguous numpy copies of a CSR batch."""
+    """paam_chainset_host over contiguous numpy copies of a CSR batch.
 
-    def __init__(self, cs):
+    units: None, or the units of every accelerator type [n_accels]
+    (Sec. IV-E); group: PAAM_UNITS_* (what the bin packing keeps together)."""
+
+    def __init__(self, cs, units=None, group=PAAM_UNITS_SEGMENT):
         self.arrays = {k: np.ascontiguousarray(getattr(cs, k), dtype=t)
                        for k, t in _HOST_DTYPES.items()}
         self.n_sets = int(cs.n_sets)
-        self.struct = paam_chainset_host(
-            n_sets=self.n_sets, **{k: v.ctypes.data for k, v in self.arrays.items()})
+        ptrs = {k: v.ctypes.data for k, v in self.arrays.items()}
+        if units is not None:
+            self.arrays["accel_units"] = np.ascontiguousarray(units, dtype=np.int16)
+            ptrs["accel_units"] = self.arrays["accel_units"].ctypes.data
+        self.struct = paam_chainset_host(n_sets=self.n_sets, unit_group=int(group), **ptrs)
 
 
 def _stream_ptr(stream) -> int | None:
@@ -158,9 +170,10 @@ class Chainset:
     """An uploaded batch: the device arena (a torch uint8 tensor) and the
     opaque library handle."""
 
-    def __init__(self, cs, device="cuda:0", stream=None):
+    def __init__(self, cs, device="cuda:0", stream=None, units=None,
+                 unit_group=PAAM_UNITS_SEGMENT):
         import torch
-        self.host = HostBatch(cs)
+        self.host = HostBatch(cs, units, unit_group)
         n = ctypes.c_size_t(0)
         check(lib().paam_chainset_bytes(ctypes.byref(self.host.struct), ctypes.byref(n)),
               "paam_chainset_bytes")
@@ -175,6 +188,18 @@ class Chainset:
         check(lib().paam_chainset_info(self.handle, info.ctypes.data), "paam_chainset_info")
         (self.n_sets, self.n_chains, self.n_callbacks, self.n_segments, self.n_subchains,
          self.max_chains, self.max_subchains, self.max_segments) = (int(v) for v in info)
+
+    def assign_units(self, stream=None):
+        """Re-runs the unit binding on the device (paam_assign_units)."""
+        check(lib().paam_assign_units(self.handle, _stream_ptr(stream)), "paam_assign_units")
+
+    def seg_units(self, stream=None):
+        """The analysed accelerator (set-local unit) of every segment, int16."""
+        import torch
+        out = torch.empty(max(self.n_segments, 1), dtype=torch.int16, device=self.device)
+        check(lib().paam_chainset_seg_units(self.handle, out.data_ptr(), _stream_ptr(stream)),
+              "paam_chainset_seg_units")
+        return out[:self.n_segments]
 
     def free(self):
         if getattr(self, "handle", None) and self.handle.value:

@@ -71,6 +71,11 @@ struct Plan {
   std::vector<uint32_t> hpx_mask;
   std::vector<double> Kd, rcp, KRr;
   std::vector<int32_t> buckets;
+  std::vector<int64_t> aeps, akappa;
+  // analysed accelerators per set: the input accelerators, or their units
+  std::vector<int64_t> set_accel_x;
+  int64_t n_types = 0;
+  int32_t unit_group = -1;
   std::vector<int64_t> work_order;
   int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0;
   std::vector<paam::SizeClass> classes;
@@ -283,15 +288,41 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
   const int64_t NG = h->cb_seg_off[NJ];
   P.n_segs = NG;
   REQ(NG == 0 || (h->A && h->accel), "segments present but A/accel null");
-  P.buckets.resize(NAc);
   for (int64_t a = 0; a < NAc; ++a) {
     REQ(h->accel_buckets[a] >= 1, "accelerator %lld: buckets < 1", (long long)a);
     REQ(h->accel_eps[a] >= 0 && h->accel_kappa[a] >= 0, "accelerator %lld: negative overhead",
         (long long)a);
     RNG(h->accel_eps[a] < kTimeLimit && h->accel_kappa[a] < kTimeLimit,
         "accelerator %lld: overhead >= 2^36 ns", (long long)a);
-    P.buckets[a] = h->accel_buckets[a];
   }
+  // units of accelerator types (Sec. IV-E): each unit is analysed as an
+  // accelerator of its own with its type's buckets and overheads
+  P.n_types = NAc;
+  P.set_accel_x.assign(h->set_accel_off, h->set_accel_off + S + 1);
+  if (h->accel_units) {
+    REQ(h->unit_group >= PAAM_UNITS_SEGMENT && h->unit_group <= PAAM_UNITS_CHAIN,
+        "unit_group %d is not a PAAM_UNITS_* value", h->unit_group);
+    P.unit_group = h->unit_group;
+    for (int64_t a = 0; a < NAc; ++a)
+      REQ(h->accel_units[a] >= 1 && h->accel_units[a] <= paam::kMaxAccel,
+          "accelerator %lld: %d units (1..%d)", (long long)a, (int)h->accel_units[a],
+          paam::kMaxAccel);
+    for (int64_t s = 0; s < S; ++s) {
+      int64_t n = 0;
+      for (int64_t a = h->set_accel_off[s]; a < h->set_accel_off[s + 1]; ++a)
+        n += h->accel_units[a];
+      RNG(n <= paam::kMaxAccel, "set %lld: %lld accelerator units (max %d)", (long long)s,
+          (long long)n, paam::kMaxAccel);
+      P.set_accel_x[s + 1] = P.set_accel_x[s] + n;
+    }
+  }
+  for (int64_t a = 0; a < NAc; ++a)
+    for (int u = 0; u < (h->accel_units ? h->accel_units[a] : 1); ++u) {
+      P.buckets.push_back(h->accel_buckets[a]);
+      P.aeps.push_back(h->accel_eps[a]);
+      P.akappa.push_back(h->accel_kappa[a]);
+    }
+  P.n_accel = P.set_accel_x[S];
 
   // pass 1: validate every set, count its sub-chains
   std::vector<int> nrun(S);
@@ -315,11 +346,13 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     const int64_t cb0 = h->chain_cb_off[c0], cb1 = h->chain_cb_off[c0 + C];
     P.max_C = std::max(P.max_C, C);
     P.max_X = std::max(P.max_X, (int32_t)(h->set_exec_off[s + 1] - h->set_exec_off[s]));
-    P.max_NA = std::max(P.max_NA, (int32_t)(h->set_accel_off[s + 1] - h->set_accel_off[s]));
+    P.max_NA = std::max(P.max_NA, (int32_t)(P.set_accel_x[s + 1] - P.set_accel_x[s]));
     P.max_runs = std::max(P.max_runs, nrun[s]);
     P.max_tot = std::max(P.max_tot, tot[s]);
     P.max_segs = std::max(P.max_segs, (int32_t)(h->cb_seg_off[cb1] - h->cb_seg_off[cb0]));
   }
+  RNG(!h->accel_units || P.max_segs <= paam::kMaxUnitSegs,
+      "a set has %d segments; with accelerator units at most %d", P.max_segs, paam::kMaxUnitSegs);
   P.n_runs = P.set_run_off[S];
   P.set_cb_off[S] = NJ;
   P.set_seg_off[S] = NG;
@@ -372,7 +405,7 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     c.count += 1;
     c.max_C = std::max(c.max_C, C);
     c.max_X = std::max(c.max_X, (int32_t)(h->set_exec_off[s + 1] - h->set_exec_off[s]));
-    c.max_NA = std::max(c.max_NA, (int32_t)(h->set_accel_off[s + 1] - h->set_accel_off[s]));
+    c.max_NA = std::max(c.max_NA, (int32_t)(P.set_accel_x[s + 1] - P.set_accel_x[s]));
     c.max_runs = std::max(c.max_runs, nrun[s]);
     c.max_segs = std::max(c.max_segs, (int32_t)(h->cb_seg_off[cb1] - h->cb_seg_off[cb0]));
   }
@@ -409,7 +442,7 @@ struct Offsets {
   size_t set_chain_off, set_cb_off, set_seg_off, set_run_off, set_exec_off, set_accel_off, eps_hop,
       work_order, T, D, Kd, rcp, KRr, rank0, chain_nrun, spin, E, cb_seg_off, A, seg_accel,
       seg_chain, seg_order, run_chain, run_exec, run_cb_lo, run_cb_hi, hpx_mask, buckets, aeps,
-      akappa, total;
+      akappa, seg_type, type_units, set_type_off, total;
 };
 
 Offsets layout(const Plan &P) {
@@ -446,6 +479,10 @@ Offsets layout(const Plan &P) {
   o.buckets = a.take<int32_t>(P.n_accel);
   o.aeps = a.take<int64_t>(P.n_accel);
   o.akappa = a.take<int64_t>(P.n_accel);
+  const bool units = P.unit_group >= 0;
+  o.seg_type = a.take<int16_t>(units ? P.n_segs : 0);
+  o.type_units = a.take<int16_t>(units ? P.n_types : 0);
+  o.set_type_off = a.take<int64_t>(units ? S + 1 : 0);
   o.total = a.off;
   return o;
 }
@@ -502,7 +539,7 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   put(buf, o.set_seg_off, P.set_seg_off.data(), S + 1);
   put(buf, o.set_run_off, P.set_run_off.data(), S + 1);
   put(buf, o.set_exec_off, h->set_exec_off, S + 1);
-  put(buf, o.set_accel_off, h->set_accel_off, S + 1);
+  put(buf, o.set_accel_off, P.set_accel_x.data(), S + 1);
   put(buf, o.eps_hop, h->eps_hop, S);
   put(buf, o.work_order, P.work_order.data(), S);
   put(buf, o.T, h->T, P.n_chains);
@@ -525,8 +562,13 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   put(buf, o.run_cb_hi, P.run_cb_hi.data(), P.n_runs);
   put(buf, o.hpx_mask, P.hpx_mask.data(), P.n_exec);
   put(buf, o.buckets, P.buckets.data(), P.n_accel);
-  put(buf, o.aeps, h->accel_eps, P.n_accel);
-  put(buf, o.akappa, h->accel_kappa, P.n_accel);
+  put(buf, o.aeps, P.aeps.data(), P.n_accel);
+  put(buf, o.akappa, P.akappa.data(), P.n_accel);
+  if (P.unit_group >= 0) {
+    put(buf, o.seg_type, h->accel, P.n_segs);
+    put(buf, o.type_units, h->accel_units, P.n_types);
+    put(buf, o.set_type_off, h->set_accel_off, S + 1);
+  }
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(d_arena, buf.data(), o.total, hipMemcpyHostToDevice, s);
@@ -574,7 +616,11 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   BIND(buckets, int32_t);
   BIND(aeps, int64_t);
   BIND(akappa, int64_t);
+  BIND(seg_type, int16_t);
+  BIND(type_units, int16_t);
+  BIND(set_type_off, int64_t);
 #undef BIND
+  b.unit_group = P.unit_group;
   b.max_C = P.max_C;
   b.max_X = P.max_X;
   b.max_NA = P.max_NA;
@@ -586,11 +632,40 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   cs->max_tot = P.max_tot;
   cs->n_classes = (int)P.classes.size();
   for (int k = 0; k < cs->n_classes; ++k) cs->cls[k] = P.classes[k];
+  if (P.unit_group >= 0) {
+    paam_status ust = paam_assign_units(cs, stream);
+    if (ust == PAAM_OK) {
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) ust = hip_fail(e, "hipStreamSynchronize(units)");
+    }
+    if (ust != PAAM_OK) {
+      delete cs;
+      return ust;
+    }
+  }
   *out = cs;
   return PAAM_OK;
 }
 
 void paam_chainset_free(paam_chainset *cs) { delete cs; }
+
+paam_status paam_assign_units(paam_chainset *cs, paam_stream stream) {
+  if (!cs) return fail(PAAM_E_INVAL, "null batch");
+  if (cs->dev.unit_group < 0) return fail(PAAM_E_STATE, "batch was uploaded without accel_units");
+  const int rc = paam::launch_units(cs->dev, num_cus(), stream);
+  if (rc != (int)hipSuccess) return hip_fail((hipError_t)rc, "units_kernel launch");
+  return PAAM_OK;
+}
+
+paam_status paam_chainset_seg_units(const paam_chainset *cs, int16_t *d_unit, paam_stream stream) {
+  if (!cs) return fail(PAAM_E_INVAL, "null batch");
+  if (cs->dev.n_segs == 0) return PAAM_OK;
+  if (!d_unit) return fail(PAAM_E_INVAL, "d_unit is null");
+  hipError_t e = hipMemcpyAsync(d_unit, cs->dev.seg_accel, (size_t)cs->dev.n_segs * sizeof(int16_t),
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(seg units)");
+  return PAAM_OK;
+}
 
 paam_status paam_chainset_info(const paam_chainset *cs, int64_t info[8]) {
   if (!cs || !info) return fail(PAAM_E_INVAL, "null argument");

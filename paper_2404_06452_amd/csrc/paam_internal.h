@@ -62,6 +62,12 @@ struct DevBatch {
   // accelerators
   const int32_t *buckets;          // [n_accels]
   const int64_t *aeps, *akappa;    // [n_accels]
+  // units of accelerator types (Sec. IV-E); the accelerators above are then
+  // the units, numbered type by type within a set
+  const int16_t *seg_type;         // [n_segs] set-local input type of each segment
+  const int16_t *type_units;       // [n_types] units of each type
+  const int64_t *set_type_off;     // [n_sets+1] types of a set
+  int32_t unit_group;              // PAAM_UNITS_*, or -1: no units (seg_accel is the input)
   // per-set maxima over the batch
   int32_t max_C, max_X, max_NA, max_runs, max_segs;
 };
@@ -181,6 +187,11 @@ struct BwdLaunch {
   float *partial;
   size_t part_stride;  // floats per chunk
 };
+
+// Binds every segment to a unit of its type (writes seg_accel in place).
+int launch_units(const DevBatch &b, int n_cus, void *stream);
+size_t units_lds_bytes(int64_t max_segs);
+constexpr int kMaxUnitSegs = 2048;  // segments per set when types have units
 
 size_t feat_wave_bytes(const DevBatch &b);
 // Feature tables of up to this size per wave live in LDS (else in the wave's

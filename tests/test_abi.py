@@ -6,6 +6,8 @@ import glob
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -129,3 +131,34 @@ def test_upload_rejects_sets_whose_tables_exceed_lds():
         hb = _paam.HostBatch(chaingen.generate(p, 1))
         assert _paam.lib().paam_chainset_bytes(ctypes.byref(hb.struct), ctypes.byref(n)) == rc, C
     assert b"LDS" in _paam.lib().paam_last_error()
+
+
+def test_unit_counts_are_validated_at_upload():
+    """Accelerator units (Sec. IV-E): counts 1..8, at most 8 units per set,
+    a known grouping, at most 2048 segments per set; the arena grows with
+    the units' tables."""
+    from paper_2404_06452_amd import _paam, chaingen
+    p = chaingen.PRESETS["small"].replace(n_accel=2)
+    cs = chaingen.generate(p, 200)
+    L = _paam.lib()
+
+    def rc(units, group=0, batch=cs):
+        hb = _paam.HostBatch(batch, units, group)
+        n = ctypes.c_size_t(0)
+        return L.paam_chainset_bytes(ctypes.byref(hb.struct), ctypes.byref(n)), n.value
+
+    na = int(cs.set_accel_off[-1])
+    st0, plain = rc(None)
+    st1, with_units = rc(np.full(na, 4, np.int16))
+    assert st0 == 0 and st1 == 0 and with_units > plain
+    assert rc(np.zeros(na, np.int16))[0] == -1
+    assert rc(np.full(na, 9, np.int16))[0] == -1
+    assert rc(np.full(na, 5, np.int16))[0] == -2       # 10 units in a set
+    assert rc(np.full(na, 2, np.int16), group=3)[0] == -1
+    for g in (0, 1, 2):
+        assert rc(np.full(na, 2, np.int16), group=g)[0] == 0
+    big = chaingen.generate(chaingen.PRESETS["small"].replace(
+        chains=(600, 600), cbs=(8, 8), pseg=(1.0, 1.0), n_exec=1), 1)
+    assert int(big.cb_seg_off[-1]) > 2048
+    assert rc(None, batch=big)[0] in (0, -2)
+    assert rc(np.ones(int(big.set_accel_off[-1]), np.int16), batch=big)[0] == -2
