@@ -545,6 +545,83 @@ def study_section(args, torch, log, net):
     return res
 
 
+def units_section(args, torch, log):
+    """Several units of one accelerator type (Sec. IV-E): segments bound to
+    units by worst-fit decreasing at upload, per segment, per callback or per
+    chain, then analysed with each unit as its own accelerator.  Schedulable
+    fraction on the study's sets against the unit count, every set compared
+    with the oracle (binding and verdict); the binding kernel's rate on sweep
+    sets."""
+    import oracle
+    from paper_2404_06452_amd import _paam, chaingen
+
+    stream = torch.cuda.Stream()
+    n = args.units_sets
+    t0 = time.perf_counter()
+    groups = (("segment", _paam.PAAM_UNITS_SEGMENT), ("callback", _paam.PAAM_UNITS_CALLBACK),
+              ("chain", _paam.PAAM_UNITS_CHAIN))
+    points = ((8, 5, 5), (8, 7, 3), (16, 5, 5))
+    res, mism = {}, 0
+    for n_chains, acc, cpu in points:
+        cs = chaingen.generate(chaingen.study_params(n_chains, acc, cpu), n)
+        key = "%d_chains_%d:%d" % (n_chains, acc, cpu)
+        res[key] = {}
+        for gname, g in groups:
+            fr = []
+            for k in (1, 2, 3, 4):
+                units = np.full(int(cs.set_accel_off[-1]), k, np.int16)
+                dev = _paam.Chainset(cs, device="cuda:0", units=units, unit_group=g)
+                su = dev.seg_units().cpu().numpy()
+                r = _paam.wcrt(dev, full=False)
+                dev.free()
+                ref = oracle.wfd_units(cs, units, g)
+                ro = oracle.wcrt(oracle.split_units(cs, units, ref), full=False,
+                                 threads=os.cpu_count() or 1)
+                mism += int((su != ref).sum()) + int((r["sched"] != ro["sched"]).sum())
+                fr.append(float((r["sched"] == 1).mean()))
+            res[key][gname] = {str(k): v for k, v in zip((1, 2, 3, 4), fr)}
+        log("units %s: %s" % (key, " | ".join(
+            "%s %s" % (gn, " ".join("%.2f" % v for v in res[key][gn].values())) for gn, _ in groups)))
+    # binding rate: sweep sets, 4 units, whole chains as items
+    m = args.units_rate_sets
+    cs = chaingen.generate("sweep", m)
+    units = np.full(int(cs.set_accel_off[-1]), 4, np.int16)
+    dev = _paam.Chainset(cs, device="cuda:0", units=units, unit_group=_paam.PAAM_UNITS_CHAIN)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        dev.assign_units(stream)
+        a.record(stream)
+        for _ in range(reps):
+            dev.assign_units(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    dt = a.elapsed_time(b) * 1e-3 / reps
+    su = dev.seg_units().cpu().numpy()
+    sample = min(m, 2000)
+    ref = oracle.wfd_units(cs.subset(range(sample)), units[:int(cs.set_accel_off[sample])],
+                           _paam.PAAM_UNITS_CHAIN)
+    mism += int((su[:len(ref)] != ref).sum())
+    dev.free()
+    out = {
+        "workload": "study sets (%d per point; 4 callbacks per chain, one segment per callback, "
+                    "one accelerator type with 1-4 units, each chain on its own executor and "
+                    "core), verdict mode" % n,
+        "schedulable_frac": res,
+        "binding": {"sets": m, "segments": int(cs.n_segments), "units_per_set": 4,
+                    "group": "chain", "ms": dt * 1e3, "sets_per_s": m / dt,
+                    "segments_per_s": cs.n_segments / dt},
+        "parity_mismatches": mism,
+        "parity": "every study set's binding and verdict, and the binding of the first %d "
+                  "sweep sets, against the oracle" % sample,
+        "setup_s": time.perf_counter() - t0,
+    }
+    log("units binding: %d sweep sets in %.3f ms (%.3g sets/s), mismatches %d" % (
+        m, dt * 1e3, m / dt, mism))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -568,6 +645,10 @@ def main():
                     help="sets of the large batch searched plainly for comparison")
     ap.add_argument("--study-sets", type=int, default=1000,
                     help="sets per point of the analytical study (0 skips it)")
+    ap.add_argument("--units-sets", type=int, default=1000,
+                    help="sets per point of the accelerator-units section (0 skips it)")
+    ap.add_argument("--units-rate-sets", type=int, default=100000,
+                    help="sweep sets whose unit binding is timed")
     ap.add_argument("--large-util", type=int, default=0,
                     help="optional second utilisation scale of the large-set section, in "
                          "permille (0: the workload's utilisation only)")
@@ -783,6 +864,9 @@ def main():
         net = None
     if args.study_sets > 0:
         line["study"] = study_section(args, torch, log, net)
+    if args.units_sets > 0:
+        line["units"] = units_section(args, torch, log)
+        mism += line["units"]["parity_mismatches"]
     print(json.dumps(line), flush=True)
     if mism:
         sys.exit(1)
