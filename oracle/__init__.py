@@ -24,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "paam_oracle.c")
+_SRC_DES = os.path.join(_HERE, "paam_des.c")
 _HDR = os.path.join(_HERE, "paam_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
@@ -45,6 +46,12 @@ class _Opts(ctypes.Structure):
                 ("bound", ctypes.c_int32)]
 
 
+class _DesOpts(ctypes.Structure):
+    _fields_ = [("n_scen", ctypes.c_int32), ("horizon", ctypes.c_int64),
+                ("exec_permille", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("util_permille", ctypes.c_int32), ("max_steps", ctypes.c_int64)]
+
+
 _DTYPES = {
     "set_chain_off": np.int64, "set_exec_off": np.int64, "set_accel_off": np.int64,
     "chain_cb_off": np.int64, "cb_seg_off": np.int64, "T": np.int64, "D": np.int64,
@@ -57,11 +64,11 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_DES), os.path.getmtime(_HDR))
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp,
-                               _SRC])
+                               _SRC, _SRC_DES])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -85,8 +92,11 @@ def _load():
                                             ctypes.c_int64, P, P, P]
         lib.oracle_wfd_range.argtypes = [ctypes.POINTER(_CS), P, ctypes.c_int32, ctypes.c_int64,
                                          ctypes.c_int64, P]
+        lib.oracle_des_range.argtypes = [ctypes.POINTER(_CS), ctypes.POINTER(_DesOpts), P,
+                                         ctypes.c_int64, ctypes.c_int64, P, P]
         for f in ("oracle_analyse_set", "oracle_segment_H", "oracle_wcrt_range",
-                  "oracle_candidate_order", "oracle_search_range", "oracle_wfd_range"):
+                  "oracle_candidate_order", "oracle_search_range", "oracle_wfd_range",
+                  "oracle_des_range"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -327,3 +337,33 @@ def split_units(cs, units, seg_unit):
     counts = np.where(off[1:] > off[:-1], per_set[:len(off) - 1] if len(per_set) else 0, 0)
     out.set_accel_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     return out
+
+
+def event_sim(cs, offsets, n_scen, horizon, exec_permille=1000, seed=0, util_permille=1000,
+        max_steps=1 << 40, sets=None, threads=1):
+    """Event-driven simulation (paam_des.c) of sets (all, or ``sets=(lo, hi)``).
+
+    ``offsets`` [n_chains * n_scen]: first releases, per set a [n_scen][C]
+    block at ``set_chain_off[set] * n_scen``.  Returns ``obs`` (same layout:
+    largest observed response, -1 none) and ``status`` [n_sets * n_scen]."""
+    lib = _load()
+    b = _Bound(cs)
+    o = _DesOpts(n_scen=n_scen, horizon=horizon, exec_permille=exec_permille,
+                 seed=seed & (2**64 - 1), util_permille=util_permille, max_steps=max_steps)
+    n = int(cs.n_sets)
+    lo, hi = (0, n) if sets is None else sets
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    obs = np.full(int(cs.set_chain_off[-1]) * n_scen, -1, np.int64)
+    status = np.full(n * n_scen, -1, np.int8)
+
+    def run(r):
+        if lib.oracle_des_range(ctypes.byref(b.s), ctypes.byref(o), off.ctypes.data, r[0], r[1],
+                                obs.ctypes.data, status.ctypes.data) != 0:
+            raise ValueError("oracle simulation rejected a set in [%d, %d)" % r)
+
+    if threads <= 1:
+        run((lo, hi))
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(run, [(lo + a, lo + b_) for a, b_ in _ranges(hi - lo, 8 * threads)]))
+    return {"obs": obs, "status": status}

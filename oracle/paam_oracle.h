@@ -91,4 +91,22 @@ int oracle_search_range(const oracle_chainsets *cs, const oracle_opts *opt, int3
 int oracle_wfd_range(const oracle_chainsets *cs, const int16_t *units, int32_t group, int64_t lo,
                      int64_t hi, int16_t *unit);
 
+/* Event-driven simulation of sets [lo, hi) (paam_des.c): n_scen scenarios
+ * per set, releases in [0, horizon].  offsets and obs are laid out per set
+ * as [n_scen][C] blocks starting at set_chain_off[set] * n_scen: the first
+ * release of every chain in, and its largest observed end-to-end response
+ * (-1: no job completed) out.  status[set * n_scen + s]: 0 done, 1 a chain
+ * needed a third live job, 2 more than max_steps time advances. */
+typedef struct {
+  int32_t n_scen;
+  int64_t horizon;
+  int32_t exec_permille;  /* 1000: WCETs; else actual times drawn from [floor(W*p/1000), W] */
+  uint64_t seed;
+  int32_t util_permille;  /* E and A enter as floor(x * util_permille / 1000) */
+  int64_t max_steps;
+} oracle_des_opts;
+
+int oracle_des_range(const oracle_chainsets *cs, const oracle_des_opts *o, const int64_t *offsets,
+                     int64_t lo, int64_t hi, int64_t *obs, int8_t *status);
+
 #endif
