@@ -330,6 +330,51 @@ paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opt
                                   void *d_ws, size_t ws_bytes, paam_stream stream);
 
 /* Thread-local description of the last failure ("" if none). */
+/* ---- Simulation (Sec. V-A: observed latencies against the bound) -------
+ * An event-driven simulation of every set under the model the analysis
+ * bounds (Sec. II-C, IV-C, IV-D, IV-F): chain c releases a job every T_c
+ * from its offset; a job runs the chain's callbacks in order, the next one
+ * ready on its executor when the previous completes (after eps_hop when the
+ * executor changes); an idle executor starts its ready callback of the
+ * highest chain priority (then the earliest release) and keeps it to the
+ * end, also while its requests are served; a callback is a CPU piece, then
+ * per segment epsilon of CPU time, the request (A + 2 kappa on the device)
+ * and a CPU piece (E split equally, the first E mod (eta+1) pieces one
+ * longer); a core runs its demanding executor of the highest process
+ * priority (an executor demands while it has CPU work, or while its request
+ * is served if its chain busy-waits); an accelerator serves its highest
+ * bucket level holding a request, one request at a time per level, highest
+ * chain priority first, then submission order, and a higher level preempts.
+ * Within an instant: releases, hop arrivals, executors by index, then
+ * accelerators by index, repeated until nothing changes; time then jumps to
+ * the next event.  A chain keeps at most two live jobs.
+ * Actual times: with exec_permille = 1000 every job runs its WCETs (after
+ * util_permille scaling); else each callback job's E and each segment's A
+ * is W - (r mod (W - floor(W * exec_permille / 1000) + 1)), r from
+ * SplitMix64 keyed by (seed, set, scenario, chain, job, callback, item).
+ * Limits: 32 chains, 16 executors, 8 segments per callback, 8 buckets per
+ * accelerator (PAAM_E_RANGE otherwise). */
+typedef struct {
+  int32_t n_scen;        /* scenarios per set, 1..2^20 */
+  int32_t exec_permille; /* 0..1000 */
+  int64_t horizon;       /* releases and completions in [0, horizon] ns, horizon < 2^40 */
+  uint64_t seed;
+  int32_t util_permille; /* 0..10^6: E and A enter as floor(x * util_permille / 1000) */
+  int32_t reserved;      /* 0 */
+  int64_t max_steps;     /* >= 1: time advances per scenario before it stops with status 2 */
+} paam_des_opts;
+
+/* d_offsets, d_obs: device int64, per set a [n_scen][C] block starting at
+ * element set_chain_off[set] * n_scen (n_chains * n_scen in all): the first
+ * release of every chain (>= 0) in; its largest observed end-to-end response
+ * (completion minus release over the jobs completed by the horizon; -1: none)
+ * out.  d_status [n_sets * n_scen] int8: 0 done, 1 a release found two live
+ * jobs of its chain (the scenario stops there), 2 max_steps reached.
+ * Asynchronous on the stream; no workspace. */
+paam_status paam_des_batch(const paam_chainset *cs, const paam_des_opts *o,
+                           const int64_t *d_offsets, int64_t *d_obs, int8_t *d_status,
+                           paam_stream stream);
+
 const char *paam_last_error(void);
 
 /* Library version string. */

@@ -22,7 +22,7 @@ PAAM_BOUND_MIN, PAAM_BOUND_L2, PAAM_BOUND_L3 = 0, 1, 2
 
 EXPORTED = (
     "paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_free", "paam_chainset_info",
-    "paam_assign_units", "paam_chainset_seg_units",
+    "paam_assign_units", "paam_chainset_seg_units", "paam_des_batch",
     "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_batch_noalloc", "paam_wcrt_autotune",
     "paam_wcrt_schedule",
     "paam_search_bytes",
@@ -48,6 +48,13 @@ class paam_chainset_host(ctypes.Structure):
 
 
 PAAM_UNITS_SEGMENT, PAAM_UNITS_CALLBACK, PAAM_UNITS_CHAIN = 0, 1, 2
+
+
+class paam_des_opts(ctypes.Structure):
+    _fields_ = [("n_scen", ctypes.c_int32), ("exec_permille", ctypes.c_int32),
+                ("horizon", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("util_permille", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_steps", ctypes.c_int64)]
 
 class paam_wcrt_opts(ctypes.Structure):
     _fields_ = [("blocking", ctypes.c_int32), ("cap_mult", ctypes.c_int32),
@@ -79,6 +86,7 @@ def lib():
         L.paam_chainset_free.restype = None
         L.paam_chainset_info.argtypes = [P, P]
         L.paam_assign_units.argtypes = [P, P]
+        L.paam_des_batch.argtypes = [P, ctypes.POINTER(paam_des_opts), P, P, P, P]
         L.paam_chainset_seg_units.argtypes = [P, P, P]
         L.paam_wcrt_bytes.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), ctypes.POINTER(S)]
         L.paam_wcrt_batch.argtypes = [P, ctypes.POINTER(paam_wcrt_opts), P, P, P, P, P, S, P]
@@ -115,7 +123,7 @@ def lib():
         L.paam_version.argtypes = []
         L.paam_version.restype = ctypes.c_char_p
         for f in ("paam_chainset_bytes", "paam_chainset_upload", "paam_chainset_info",
-                  "paam_assign_units", "paam_chainset_seg_units",
+                  "paam_assign_units", "paam_chainset_seg_units", "paam_des_batch",
                   "paam_wcrt_bytes", "paam_wcrt_batch", "paam_wcrt_batch_noalloc", "paam_search_bytes",
                   "paam_priority_search"):
             getattr(L, f).restype = ctypes.c_int32
@@ -497,3 +505,30 @@ def score(cs: Chainset, net: Network, n_cand: int, seed: int, stream=None, **wcr
     ws = workspace(paam_score_bytes(cs, o), cs.device)
     paam_score_candidates(cs, o, net.params, net.packed, scores, ws, stream)
     return scores
+
+
+def des_opts(n_scen, horizon, exec_permille=1000, seed=0, util_permille=1000,
+             max_steps=1 << 40) -> paam_des_opts:
+    return paam_des_opts(n_scen=n_scen, exec_permille=exec_permille, horizon=horizon,
+                         seed=seed & (2**64 - 1), util_permille=util_permille, reserved=0,
+                         max_steps=max_steps)
+
+
+def paam_des_batch(cs: Chainset, opts: paam_des_opts, offsets, obs, status, stream=None) -> None:
+    check(lib().paam_des_batch(cs.handle, ctypes.byref(opts), offsets.data_ptr(), obs.data_ptr(),
+                               status.data_ptr(), _stream_ptr(stream)), "paam_des_batch")
+
+
+def simulate(cs: Chainset, offsets, n_scen, horizon, stream=None, **kw) -> dict:
+    """Event-driven simulation of every set in n_scen scenarios
+    (paam_des_batch); offsets [n_chains * n_scen] int64 (per set a
+    [n_scen][C] block).  Returns host arrays obs (same layout) and status."""
+    import torch
+    o = des_opts(n_scen, horizon, **kw)
+    off = torch.as_tensor(np.ascontiguousarray(offsets, np.int64)).to(cs.device)
+    obs = torch.empty(max(cs.n_chains * n_scen, 1), dtype=torch.int64, device=cs.device)
+    status = torch.empty(max(cs.n_sets * n_scen, 1), dtype=torch.int8, device=cs.device)
+    paam_des_batch(cs, o, off, obs, status, stream)
+    _sync(cs.device)
+    return {"obs": obs.cpu().numpy()[:cs.n_chains * n_scen],
+            "status": status.cpu().numpy()[:cs.n_sets * n_scen]}

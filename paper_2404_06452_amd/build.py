@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBPAAM = os.path.join(PKG, "libpaam.so")
 
-SOURCES = ["paam_host.cpp", "paam_kernels.hip", "paam_surrogate.hip", "paam_units.hip"]
+SOURCES = ["paam_host.cpp", "paam_kernels.hip", "paam_surrogate.hip", "paam_units.hip", "paam_des.hip"]
 HEADERS = [os.path.join(CSRC, h) for h in ("paam_internal.h", "paam_device.h")] + [
     os.path.join(INCLUDE, "paam.h")]
 

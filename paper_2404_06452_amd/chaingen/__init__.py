@@ -385,3 +385,19 @@ def training_triples(n_sets: int, n_samples: int, n_cand: int, util_range: tuple
 def shuffle_order(n: int, seed: int) -> np.ndarray:
     """int64 [n]: a seeded permutation (the visiting order of one epoch)."""
     return np.random.default_rng(seed).permutation(n).astype(np.int64)
+
+
+def release_offsets(cs: ChainSets, n_scen: int, seed: int) -> np.ndarray:
+    """First release of every chain in every scenario of a simulation:
+    scenario 0 releases every chain at 0 (the synchronous release), the
+    others uniformly in [0, T_c).  Layout: per set a [n_scen][C] block at
+    set_chain_off[set] * n_scen."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(int(cs.set_chain_off[-1]) * n_scen, np.int64)
+    for s in range(cs.n_sets):
+        c0, c1 = int(cs.set_chain_off[s]), int(cs.set_chain_off[s + 1])
+        T = np.asarray(cs.T[c0:c1], np.int64)
+        blk = (rng.random((n_scen, c1 - c0)) * T).astype(np.int64)
+        blk[0] = 0
+        out[c0 * n_scen:c1 * n_scen] = blk.ravel()
+    return out

@@ -68,6 +68,8 @@ struct Plan {
   std::vector<int16_t> run_chain, run_exec;
   std::vector<int32_t> run_cb_lo, run_cb_hi, chain_nrun, seg_order;
   std::vector<int16_t> rank0, seg_chain;
+  std::vector<int8_t> cb_exec;
+  std::vector<int32_t> chain_cb_lo;
   std::vector<uint32_t> hpx_mask;
   std::vector<double> Kd, rcp, KRr;
   std::vector<int32_t> buckets;
@@ -76,6 +78,7 @@ struct Plan {
   std::vector<int64_t> set_accel_x;
   int64_t n_types = 0;
   int32_t unit_group = -1;
+  int32_t max_cb_segs = 0, max_buckets = 0;
   std::vector<int64_t> work_order;
   int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0;
   std::vector<paam::SizeClass> classes;
@@ -225,8 +228,11 @@ void fill_set(const paam_chainset_host *h, int64_t s, Plan &P) {
         runs.back().hi = jl + 1;
       }
     }
-    for (int64_t j = h->chain_cb_off[c0 + c]; j < h->chain_cb_off[c0 + c + 1]; ++j)
+    for (int64_t j = h->chain_cb_off[c0 + c]; j < h->chain_cb_off[c0 + c + 1]; ++j) {
       for (int64_t g = h->cb_seg_off[j]; g < h->cb_seg_off[j + 1]; ++g) P.seg_chain[g] = (int16_t)c;
+      P.cb_exec[j] = (int8_t)h->exec[j];
+    }
+    P.chain_cb_lo[c0 + c] = (int32_t)(h->chain_cb_off[c0 + c] - cb0);
   }
   for (const Run &r : runs) P.chain_nrun[c0 + r.chain]++;
   std::stable_sort(runs.begin(), runs.end(), [&](const Run &a, const Run &b) {
@@ -283,8 +289,11 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
   const int64_t NJ = h->chain_cb_off[NC];
   P.n_cbs = NJ;
   REQ(h->cb_seg_off[0] == 0, "cb_seg_off must start at 0");
-  for (int64_t j = 0; j < NJ; ++j)
+  for (int64_t j = 0; j < NJ; ++j) {
     REQ(h->cb_seg_off[j + 1] >= h->cb_seg_off[j], "cb_seg_off decreases at %lld", (long long)j);
+    P.max_cb_segs = std::max<int32_t>(P.max_cb_segs, (int32_t)std::min<int64_t>(
+                                                         h->cb_seg_off[j + 1] - h->cb_seg_off[j], 1 << 30));
+  }
   const int64_t NG = h->cb_seg_off[NJ];
   P.n_segs = NG;
   REQ(NG == 0 || (h->A && h->accel), "segments present but A/accel null");
@@ -294,6 +303,7 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
         (long long)a);
     RNG(h->accel_eps[a] < kTimeLimit && h->accel_kappa[a] < kTimeLimit,
         "accelerator %lld: overhead >= 2^36 ns", (long long)a);
+    P.max_buckets = std::max<int32_t>(P.max_buckets, h->accel_buckets[a]);
   }
   // units of accelerator types (Sec. IV-E): each unit is analysed as an
   // accelerator of its own with its type's buckets and overheads
@@ -369,6 +379,8 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
   P.chain_nrun.assign(NC, 0);
   P.seg_chain.resize(NG);
   P.seg_order.resize(NG);
+  P.cb_exec.resize(NJ);
+  P.chain_cb_lo.resize(NC);
   P.hpx_mask.assign(NX, 0u);
   P.run_chain.resize(P.n_runs);
   P.run_exec.resize(P.n_runs);
@@ -440,7 +452,8 @@ struct Arena {
 
 struct Offsets {
   size_t set_chain_off, set_cb_off, set_seg_off, set_run_off, set_exec_off, set_accel_off, eps_hop,
-      work_order, T, D, Kd, rcp, KRr, rank0, chain_nrun, spin, E, cb_seg_off, A, seg_accel,
+      work_order, T, D, Kd, rcp, KRr, rank0, chain_nrun, spin, E, cb_seg_off, cb_exec, chain_cb_lo,
+      A, seg_accel,
       seg_chain, seg_order, run_chain, run_exec, run_cb_lo, run_cb_hi, hpx_mask, buckets, aeps,
       akappa, seg_type, type_units, set_type_off, total;
 };
@@ -467,6 +480,8 @@ Offsets layout(const Plan &P) {
   o.spin = a.take<uint8_t>(P.n_chains);
   o.E = a.take<int64_t>(P.n_cbs);
   o.cb_seg_off = a.take<int64_t>(P.n_cbs + 1);
+  o.cb_exec = a.take<int8_t>(P.n_cbs);
+  o.chain_cb_lo = a.take<int32_t>(P.n_chains);
   o.A = a.take<int64_t>(P.n_segs);
   o.seg_accel = a.take<int16_t>(P.n_segs);
   o.seg_chain = a.take<int16_t>(P.n_segs);
@@ -552,6 +567,8 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   put(buf, o.spin, h->spin, P.n_chains);
   put(buf, o.E, h->E, P.n_cbs);
   put(buf, o.cb_seg_off, h->cb_seg_off, P.n_cbs + 1);
+  put(buf, o.cb_exec, P.cb_exec.data(), P.n_cbs);
+  put(buf, o.chain_cb_lo, P.chain_cb_lo.data(), P.n_chains);
   put(buf, o.A, h->A, P.n_segs);
   put(buf, o.seg_accel, h->accel, P.n_segs);
   put(buf, o.seg_chain, P.seg_chain.data(), P.n_segs);
@@ -604,6 +621,8 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   BIND(spin, uint8_t);
   BIND(E, int64_t);
   BIND(cb_seg_off, int64_t);
+  BIND(cb_exec, int8_t);
+  BIND(chain_cb_lo, int32_t);
   BIND(A, int64_t);
   BIND(seg_accel, int16_t);
   BIND(seg_chain, int16_t);
@@ -630,6 +649,8 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   cs->n_exec = P.n_exec;
   cs->n_accel = P.n_accel;
   cs->max_tot = P.max_tot;
+  cs->max_cb_segs = P.max_cb_segs;
+  cs->max_buckets = P.max_buckets;
   cs->n_classes = (int)P.classes.size();
   for (int k = 0; k < cs->n_classes; ++k) cs->cls[k] = P.classes[k];
   if (P.unit_group >= 0) {
@@ -648,6 +669,41 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
 }
 
 void paam_chainset_free(paam_chainset *cs) { delete cs; }
+
+paam_status paam_des_batch(const paam_chainset *cs, const paam_des_opts *o,
+                           const int64_t *d_offsets, int64_t *d_obs, int8_t *d_status,
+                           paam_stream stream) {
+  if (!cs || !o) return fail(PAAM_E_INVAL, "null argument");
+  if (o->n_scen < 1 || o->n_scen > (1 << 20)) return fail(PAAM_E_INVAL, "n_scen outside 1..2^20");
+  if (o->exec_permille < 0 || o->exec_permille > 1000)
+    return fail(PAAM_E_INVAL, "exec_permille outside 0..1000");
+  if (o->util_permille < 0 || o->util_permille > 1000000)
+    return fail(PAAM_E_INVAL, "util_permille outside 0..10^6");
+  if (o->horizon < 0 || o->horizon >= ((int64_t)1 << 40))
+    return fail(PAAM_E_RANGE, "horizon outside [0, 2^40)");
+  if (o->max_steps < 1 || o->reserved != 0) return fail(PAAM_E_INVAL, "max_steps < 1 or reserved != 0");
+  const paam::DevBatch &b = cs->dev;
+  if (b.max_C > paam::kDesChains || b.max_X > paam::kDesExec || cs->max_cb_segs > paam::kDesSegs ||
+      cs->max_buckets > paam::kDesLevels)
+    return fail(PAAM_E_RANGE,
+                "simulation holds at most %d chains, %d executors, %d segments per callback and "
+                "%d buckets per accelerator per set",
+                paam::kDesChains, paam::kDesExec, paam::kDesSegs, paam::kDesLevels);
+  if (b.n_sets == 0) return PAAM_OK;
+  if (!d_offsets || !d_obs || !d_status) return fail(PAAM_E_INVAL, "null device buffer");
+  paam::DesLaunch L;
+  L.b = b;
+  L.o = *o;
+  L.offsets = d_offsets;
+  L.obs = d_obs;
+  L.status = d_status;
+  const int64_t work = b.n_sets * ((o->n_scen + paam::kWave - 1) / paam::kWave);
+  const int64_t want = (int64_t)num_cus() * 16;
+  L.grid = (int)std::min<int64_t>(work, want);
+  const int rc = paam::launch_des(L, stream);
+  if (rc != (int)hipSuccess) return hip_fail((hipError_t)rc, "des_kernel launch");
+  return PAAM_OK;
+}
 
 paam_status paam_assign_units(paam_chainset *cs, paam_stream stream) {
   if (!cs) return fail(PAAM_E_INVAL, "null batch");

@@ -47,6 +47,8 @@ struct DevBatch {
   // callbacks
   const int64_t *E;            // [n_cbs]
   const int64_t *cb_seg_off;   // [n_cbs+1] global segment offsets
+  const int8_t *cb_exec;       // [n_cbs] set-local executor of the callback
+  const int32_t *chain_cb_lo;  // [n_chains] set-local first callback of the chain
   // segments
   const int64_t *A;            // [n_segs]
   const int16_t *seg_accel;    // [n_segs]
@@ -94,6 +96,7 @@ struct paam_chainset {
   size_t arena_bytes;
   int64_t n_exec, n_accel;
   int64_t max_tot;  // largest total demand of a set: sum of E, A + 2 kappa and epsilon
+  int32_t max_cb_segs, max_buckets;  // largest eta of a callback, most buckets of an accelerator
   int n_classes;
   paam::SizeClass cls[paam::kMaxClasses];
 };
@@ -192,6 +195,21 @@ struct BwdLaunch {
 int launch_units(const DevBatch &b, int n_cus, void *stream);
 size_t units_lds_bytes(int64_t max_segs);
 constexpr int kMaxUnitSegs = 2048;  // segments per set when types have units
+
+// Event-driven simulation (paam_des.hip): one lane per scenario.
+constexpr int kDesChains = 32;  // chains per set
+constexpr int kDesExec = 16;    // executors per set
+constexpr int kDesSegs = 8;     // segments per callback
+constexpr int kDesLevels = 8;   // buckets per accelerator
+struct DesLaunch {
+  DevBatch b;
+  paam_des_opts o;
+  const int64_t *offsets;
+  int64_t *obs;
+  int8_t *status;
+  int grid;
+};
+int launch_des(const DesLaunch &L, void *stream);
 
 size_t feat_wave_bytes(const DevBatch &b);
 // Feature tables of up to this size per wave live in LDS (else in the wave's

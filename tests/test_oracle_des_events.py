@@ -16,30 +16,7 @@ import oracle
 import oracle.des as unit_step
 from paper_2404_06452_amd import chaingen
 
-
-def _rand_set(rng):
-    C, X = rng.randint(1, 4), rng.randint(1, 3)
-    cores, NA = rng.randint(1, X), rng.randint(1, 2)
-    exec_core = [rng.randrange(cores) for _ in range(X)]
-    exec_prio = []
-    for e in range(X):
-        used = {exec_prio[f] for f in range(e) if exec_core[f] == exec_core[e]}
-        p = rng.randint(1, 5)
-        while p in used:
-            p += 1
-        exec_prio.append(p)
-    prios = rng.sample(range(1, 20), C)
-    chains = []
-    for c in range(C):
-        T = rng.randint(20, 80)
-        cbs = [{"E": rng.randint(0, 3), "exec": rng.randrange(X),
-                "segs": [[rng.randint(0, 3), rng.randrange(NA)] for _ in range(rng.randint(0, 2))]}
-               for _ in range(rng.randint(1, 3))]
-        chains.append({"T": T, "D": T, "prio": prios[c], "spin": rng.randint(0, 1), "cbs": cbs})
-    return {"chains": chains, "exec_core": exec_core, "exec_prio": exec_prio,
-            "accel_buckets": [rng.randint(1, 2) for _ in range(NA)],
-            "accel_eps": [rng.randint(0, 2) for _ in range(NA)],
-            "accel_kappa": [rng.randint(0, 1) for _ in range(NA)], "eps_hop": rng.randint(0, 2)}
+from des_sets import tiny_set
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -47,7 +24,7 @@ def test_events_equal_unit_steps(seed):
     rng = random.Random(seed)
     compared = observed = 0
     for _ in range(120):
-        st = _rand_set(rng)
+        st = tiny_set(rng)
         cs = chaingen.from_sets([st])
         C, S, H = len(st["chains"]), 3, 200
         offs = [[0] * C] + [[rng.randrange(ch["T"]) for ch in st["chains"]] for _ in range(S - 1)]
