@@ -622,6 +622,117 @@ def units_section(args, torch, log):
     return out
 
 
+def des_section(args, torch, log):
+    """Observed latencies against the bound at scale (the method of the
+    paper's Case Study 1, Sec. V-A).  Two workloads: the study's 8-chain sets
+    (accelerator : CPU 1:1, every chain on its own executor and core), and
+    the small sets (8 chains on two executors that share a core) at 25 % of
+    their utilisation, where executor blocking matters.  Every set runs 64
+    scenarios (synchronous release, then random offsets), with every job at
+    its WCET and again with actual times drawn from [W/2, W].  Every observed
+    end-to-end latency of an admitted set is compared with the analysis
+    bound (SAFE blocking), and with the bound under the printed blocking term
+    of Eq. (5)/(6) for contrast; the kernel's rate; the oracle on a sample,
+    bit-exact, and its single-thread rate."""
+    import oracle
+    from paper_2404_06452_amd import _paam, chaingen
+
+    stream = torch.cuda.Stream()
+    n, n_scen = args.des_sets, 64
+    t0 = time.perf_counter()
+    INF = np.iinfo(np.int64).max
+    out = {}
+    workloads = (
+        ("study_8_chains", chaingen.generate(chaingen.study_params(8, 1, 1), n), 1000,
+         "study sets: 8 chains x 4 callbacks, one segment per callback, accelerator : CPU 1:1, "
+         "each chain on its own executor and core"),
+        ("small_25pct", chaingen.generate("small", n), 250,
+         "small sets at 25 % of their utilisation: 8 chains x 2-5 callbacks on two executors "
+         "sharing a core, 30 % of callbacks with a segment"),
+    )
+    for name, cs, util, what in workloads:
+        horizon = int(2 * cs.T.max())
+        offs = chaingen.release_offsets(cs, n_scen, 2404)
+        dev = _paam.Chainset(cs, device="cuda:0")
+        safe = _paam.wcrt(dev, full=True, util_permille=util)
+        paper = _paam.wcrt(dev, full=True, util_permille=util, blocking=_paam.PAAM_BLOCK_PAPER)
+        d_off = torch.as_tensor(offs).cuda()
+        obs = torch.empty(cs.n_chains * n_scen, dtype=torch.int64, device="cuda:0")
+        status = torch.empty(n * n_scen, dtype=torch.int8, device="cuda:0")
+        m = min(n, 2000)
+        jobs = 0
+        for s_ in range(m):
+            c0, c1 = int(cs.set_chain_off[s_]), int(cs.set_chain_off[s_ + 1])
+            blk = offs[c0 * n_scen:c1 * n_scen].reshape(n_scen, c1 - c0)
+            jobs += int(((horizon - blk) // cs.T[c0:c1] + 1).sum())
+        jobs_per_set = jobs / m
+        chain_set = np.repeat(np.arange(n), np.diff(cs.set_chain_off))
+        adm = (safe["sched"] == 1)[chain_set]
+        padm_sets = paper["sched"] == 1
+        res = {"workload": "%d %s; %d scenarios per set (0: synchronous release; others: offsets "
+                           "uniform in [0, T)); horizon %.3f s; utilisation scale %d permille" % (
+                               n, what, n_scen, horizon * 1e-9, util),
+               "admitted_sets": int((safe["sched"] == 1).sum()),
+               "admitted_sets_printed_blocking": int(padm_sets.sum()),
+               "jobs_per_scenario_mean": jobs_per_set / n_scen}
+        for label, ex in (("wcet", 1000), ("actual_50_100pct", 500)):
+            o = _paam.des_opts(n_scen, horizon, exec_permille=ex, seed=7, util_permille=util)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                a.record(stream)
+                _paam.paam_des_batch(dev, o, d_off, obs, status, stream)
+                b.record(stream)
+            torch.cuda.synchronize()
+            dt = a.elapsed_time(b) * 1e-3
+            g = obs.cpu().numpy()
+            st = status.cpu().numpy()
+            per = np.full(cs.n_chains, -1, np.int64)  # largest observation over the scenarios
+            for s_ in range(n):
+                c0, c1 = int(cs.set_chain_off[s_]), int(cs.set_chain_off[s_ + 1])
+                per[c0:c1] = g[c0 * n_scen:c1 * n_scen].reshape(n_scen, c1 - c0).max(0)
+            ok = adm & (per >= 0)
+            ratio = per[ok] / safe["chain_R"][ok]
+            fin = (paper["chain_R"] < INF) & (per >= 0)
+            miss = np.zeros(n, bool)  # a latency above the deadline, or a chain two jobs behind
+            np.logical_or.at(miss, chain_set, per > cs.D)
+            miss |= (st.reshape(n, n_scen) == 1).any(1)
+            r = {
+                "ms": dt * 1e3, "scenarios_per_s": n * n_scen / dt,
+                "jobs_per_s": jobs_per_set * n / dt,
+                "status_counts": {str(k): int((st == k).sum()) for k in (0, 1, 2)},
+                "chains_observed_in_admitted_sets": int(ok.sum()),
+                "above_bound": int((per[ok] > safe["chain_R"][ok]).sum()),
+                "observed_over_bound_mean": float(ratio.mean()) if ratio.size else None,
+                "observed_over_bound_max": float(ratio.max()) if ratio.size else None,
+                "above_printed_blocking_bound": int((per[fin] > paper["chain_R"][fin]).sum()),
+                "printed_admitted_sets_with_observed_miss": int((padm_sets & miss).sum()),
+            }
+            k_sets = args.des_oracle_sets
+            sub = cs.subset(range(k_sets))
+            tc = time.perf_counter()
+            ro = oracle.event_sim(sub, offs[:int(sub.set_chain_off[-1]) * n_scen], n_scen, horizon,
+                                  exec_permille=ex, seed=7, util_permille=util)
+            tc = time.perf_counter() - tc
+            k = int(sub.set_chain_off[-1]) * n_scen
+            r["oracle"] = {"sets": k_sets, "threads": 1, "s": tc,
+                           "scenarios_per_s": k_sets * n_scen / tc,
+                           "mismatches": int((ro["obs"] != g[:k]).sum()) +
+                           int((ro["status"] != st[:k_sets * n_scen]).sum())}
+            res[label] = r
+            log("des %s %s: %d x %d scenarios in %.1f ms (%.3g/s, oracle %.3g/s on one thread, "
+                "%d mismatches); above bound %d of %d chains; obs/bound mean %.3f max %.3f; above "
+                "printed-blocking bound %d; printed-admitted sets with an observed miss %d" % (
+                    name, label, n, n_scen, dt * 1e3, n * n_scen / dt,
+                    r["oracle"]["scenarios_per_s"], r["oracle"]["mismatches"], r["above_bound"],
+                    ok.sum(), r["observed_over_bound_mean"] or 0, r["observed_over_bound_max"] or 0,
+                    r["above_printed_blocking_bound"], r["printed_admitted_sets_with_observed_miss"]))
+        dev.free()
+        out[name] = res
+    out["setup_s"] = time.perf_counter() - t0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -649,6 +760,10 @@ def main():
                     help="sets per point of the accelerator-units section (0 skips it)")
     ap.add_argument("--units-rate-sets", type=int, default=100000,
                     help="sweep sets whose unit binding is timed")
+    ap.add_argument("--des-sets", type=int, default=10000,
+                    help="sets of the simulation section (64 scenarios each; 0 skips it)")
+    ap.add_argument("--des-oracle-sets", type=int, default=20,
+                    help="sets the simulation oracle repeats, bit-exact, on one thread")
     ap.add_argument("--large-util", type=int, default=0,
                     help="optional second utilisation scale of the large-set section, in "
                          "permille (0: the workload's utilisation only)")
@@ -867,6 +982,10 @@ def main():
     if args.units_sets > 0:
         line["units"] = units_section(args, torch, log)
         mism += line["units"]["parity_mismatches"]
+    if args.des_sets > 0:
+        line["des"] = des_section(args, torch, log)
+        mism += sum(line["des"][w][k]["oracle"]["mismatches"] for w in ("study_8_chains", "small_25pct")
+                    for k in ("wcet", "actual_50_100pct"))
     print(json.dumps(line), flush=True)
     if mism:
         sys.exit(1)

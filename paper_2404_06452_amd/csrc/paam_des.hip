@@ -5,9 +5,10 @@
 //
 // A wave takes 64 scenarios of one set, so every lane reads the same set
 // tables while it runs its own timeline; lanes never synchronise.  A lane's
-// state (two job slots per chain, executors, the request being served on
-// every bucket level) lives in private arrays, whose per-lane interleaving
-// makes accesses to one slot index coalesce across the wave.
+// job slots (two per chain) and the request served on every bucket level
+// live in private arrays; which slots are live, ready, travelling or queued,
+// which executors run or wait, and which levels are occupied are bit masks
+// in registers.
 //
 // The model (Sec. II-C, IV-C, IV-D, IV-F):
 //  * releases every T from the chain's offset; callbacks in chain order; the
@@ -37,7 +38,6 @@ namespace paam {
 namespace {
 
 constexpr int kSlots = 2 * kDesChains;
-enum : int8_t { kFree = 0, kReady = 1, kHop = 2, kRun = 3 };
 
 // SplitMix64 output function (Steele, Lea and Flood, 2014).
 __device__ inline uint64_t sm_mix(uint64_t z) {
@@ -53,7 +53,7 @@ struct Slot {
                    // the arrival time while the job travels between executors
   int64_t rleft;   // remaining service of the submitted request
   int32_t job, seq, cb;  // cb: set-local callback
-  int8_t state, exec, pos, queued, ra, rl;
+  int8_t exec, pos, ra, rl;
 };
 
 struct Sim {
@@ -96,6 +96,19 @@ __device__ int level_of(const Sim &s, const uint8_t *amask, int c, int a) {
   return (int)((int64_t)r * b.buckets[s.a0 + a] / m);
 }
 
+// Slot sets, executor sets and occupied bucket levels are bit masks held in
+// registers, so the per-instant scans touch only the slots that matter (the
+// ready, travelling or queued ones); the per-slot fields live in private
+// memory.  Executor e's running slot is byte e of run_lo/run_hi.
+__device__ inline int run_slot(uint64_t lo, uint64_t hi, int e) {
+  return (int)(((e < 8 ? lo : hi) >> (8 * (e & 7))) & 0xff);
+}
+__device__ inline void set_run_slot(uint64_t &lo, uint64_t &hi, int e, int v) {
+  uint64_t &w = e < 8 ? lo : hi;
+  const int sh = 8 * (e & 7);
+  w = (w & ~(0xffull << sh)) | ((uint64_t)v << sh);
+}
+
 __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t *status) {
   const DevBatch &b = *s.b;
   const paam_des_opts &o = *s.o;
@@ -105,21 +118,22 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
   int64_t rel[kDesChains], worst[kDesChains];
   int32_t njob[kDesChains];
   uint8_t amask[kDesChains];
-  int8_t run[kDesExec], wait[kDesExec], cur[kMaxAccel * kDesLevels];
-  for (int i = 0; i < 2 * C; ++i) sl[i].state = kFree, sl[i].queued = 0;
+  int8_t cur[kMaxAccel * kDesLevels];
+  uint64_t live = 0, ready = 0, hopm = 0, queued = 0, busy = 0;  // slots; levels a*8+l
+  uint32_t runm = 0, waitm = 0, spinm = 0;                         // executors
+  uint64_t run_lo = 0, run_hi = 0;
+  int64_t next_rel = INT64_MAX;
   for (int c = 0; c < C; ++c) {
     rel[c] = offs[c];
+    next_rel = rel[c] < next_rel ? rel[c] : next_rel;
     worst[c] = -1;
     njob[c] = 0;
     amask[c] = 0;
   }
-  // accelerator use per chain (segments are grouped by chain in set order)
   {
     const int64_t gs = b.set_seg_off[s.set], ge = b.set_seg_off[s.set + 1];
     for (int64_t g = gs; g < ge; ++g) amask[b.seg_chain[g]] |= (uint8_t)(1u << b.seg_accel[g]);
   }
-  for (int e = 0; e < X; ++e) run[e] = -1, wait[e] = 0;
-  for (int i = 0; i < NA * kDesLevels; ++i) cur[i] = -1;
   int32_t seq = 0;
   int64_t t = 0, steps = 0;
   int8_t st = 0;
@@ -129,38 +143,46 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
     while (changed) {
       changed = false;
       // releases
-      for (int c = 0; c < C; ++c)
-        while (rel[c] <= t && rel[c] <= o.horizon) {
-          const int32_t k = njob[c]++;
-          Slot &x = sl[2 * c + (k & 1)];
-          if (x.state != kFree) {
-            st = 1;
-            goto done;
+      if (next_rel <= t) {
+        next_rel = INT64_MAX;
+        for (int c = 0; c < C; ++c) {
+          while (rel[c] <= t && rel[c] <= o.horizon) {
+            const int32_t k = njob[c]++;
+            const int i = 2 * c + (k & 1);
+            if ((live >> i) & 1) {
+              st = 1;
+              goto done;
+            }
+            Slot &x = sl[i];
+            x.release = rel[c];
+            x.job = k;
+            x.cb = b.chain_cb_lo[s.c0 + c];
+            x.exec = b.cb_exec[s.j0 + x.cb];
+            live |= 1ull << i;
+            ready |= 1ull << i;
+            rel[c] += b.T[s.c0 + c];
+            changed = true;
           }
-          x.release = rel[c];
-          x.job = k;
-          x.cb = b.chain_cb_lo[s.c0 + c];
-          x.state = kReady;
-          x.exec = b.cb_exec[s.j0 + x.cb];
-          x.queued = 0;
-          x.pos = 0;
-          x.left = -1;
-          rel[c] += b.T[s.c0 + c];
-          changed = true;
+          next_rel = rel[c] < next_rel ? rel[c] : next_rel;
         }
+      }
       // hop arrivals
-      for (int i = 0; i < 2 * C; ++i)
-        if (sl[i].state == kHop && sl[i].left <= t) {
-          sl[i].state = kReady;
+      for (uint64_t m = hopm; m; m &= m - 1) {
+        const int i = __builtin_ctzll(m);
+        if (sl[i].left <= t) {
+          hopm &= ~(1ull << i);
+          ready |= 1ull << i;
           sl[i].exec = b.cb_exec[s.j0 + sl[i].cb];
           changed = true;
         }
+      }
       // executors
       for (int e = 0; e < X; ++e) {
-        if (run[e] < 0) {
+        if (!((runm >> e) & 1) && ready) {
           int best = -1, brank = 0;
-          for (int i = 0; i < 2 * C; ++i) {
-            if (sl[i].state != kReady || sl[i].exec != e) continue;
+          for (uint64_t m = ready; m; m &= m - 1) {
+            const int i = __builtin_ctzll(m);
+            if (sl[i].exec != e) continue;
             const int ri = b.rank0[s.c0 + (i >> 1)];
             if (best < 0 || ri < brank || (ri == brank && sl[i].release < sl[best].release)) {
               best = i;
@@ -168,16 +190,19 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
             }
           }
           if (best >= 0) {
-            run[e] = (int8_t)best;
-            sl[best].state = kRun;
+            ready &= ~(1ull << best);
+            runm |= 1u << e;
+            set_run_slot(run_lo, run_hi, e, best);
+            if (b.spin[s.c0 + (best >> 1)]) spinm |= 1u << e; else spinm &= ~(1u << e);
             sl[best].pos = 0;
             sl[best].left = -1;
             changed = true;
           }
         }
-        if (run[e] >= 0 && !wait[e]) {
-          Slot &x = sl[run[e]];
-          const int c = run[e] >> 1;
+        if (((runm & ~waitm) >> e) & 1) {
+          const int i = run_slot(run_lo, run_hi, e);
+          Slot &x = sl[i];
+          const int c = i >> 1;
           const int64_t g0 = b.cb_seg_off[s.j0 + x.cb];
           const int eta = (int)(b.cb_seg_off[s.j0 + x.cb + 1] - g0);
           const int cb_lo = b.chain_cb_lo[s.c0 + c];
@@ -186,20 +211,20 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
           const int n_items = 1 + 3 * eta;
           for (;;) {
             if (x.pos >= n_items) {  // the callback completes
-              run[e] = -1;
-              wait[e] = 0;
+              runm &= ~(1u << e);
+              waitm &= ~(1u << e);
               if (x.cb + 1 == cb_hi) {
                 const int64_t r = t - x.release;
                 if (r > worst[c]) worst[c] = r;
-                x.state = kFree;
+                live &= ~(1ull << i);
               } else {
                 x.cb += 1;
                 const int nx = b.cb_exec[s.j0 + x.cb];
                 if (nx != e && hop > 0) {
-                  x.state = kHop;
+                  hopm |= 1ull << i;
                   x.left = t + hop;
                 } else {
-                  x.state = kReady;
+                  ready |= 1ull << i;
                   x.exec = (int8_t)nx;
                 }
               }
@@ -211,13 +236,13 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
               if (x.left == -1) {
                 const int k = (x.pos - 1) / 3;
                 const int a = b.seg_accel[g0 + k];
-                x.queued = 1;
+                queued |= 1ull << i;
                 x.ra = (int8_t)a;
                 x.rl = (int8_t)level_of(s, amask, c, a);
                 x.rleft = actual(s, c, x.job, cbl, k, scaled(s, b.A[g0 + k])) + 2 * b.akappa[s.a0 + a];
                 x.seq = seq++;
                 x.left = -2;
-                wait[e] = 1;
+                waitm |= 1u << e;
                 changed = true;
               }
               break;
@@ -242,11 +267,12 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
       for (int a = 0; a < NA; ++a) {
         const int nb = b.buckets[s.a0 + a];
         for (int l = 0; l < nb; ++l) {
-          int8_t &q = cur[a * kDesLevels + l];
-          if (q < 0) {
+          const int q = a * kDesLevels + l;
+          if (!((busy >> q) & 1) && queued) {
             int best = -1, brank = 0;
-            for (int i = 0; i < 2 * C; ++i) {
-              if (!sl[i].queued || sl[i].ra != a || sl[i].rl != l) continue;
+            for (uint64_t m = queued; m; m &= m - 1) {
+              const int i = __builtin_ctzll(m);
+              if (sl[i].ra != a || sl[i].rl != l) continue;
               const int ri = b.rank0[s.c0 + (i >> 1)];
               if (best < 0 || ri < brank || (ri == brank && sl[i].seq < sl[best].seq)) {
                 best = i;
@@ -254,17 +280,18 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
               }
             }
             if (best >= 0) {
-              q = (int8_t)best;
-              sl[best].queued = 0;
+              cur[q] = (int8_t)best;
+              busy |= 1ull << q;
+              queued &= ~(1ull << best);
             }
           }
-          if (q >= 0) {
-            Slot &x = sl[q];
+          if ((busy >> q) & 1) {
+            Slot &x = sl[cur[q]];
             if (x.rleft == 0) {
-              q = -1;
+              busy &= ~(1ull << q);
               x.pos += 1;
               x.left = -1;
-              wait[x.exec] = 0;
+              waitm &= ~(1u << x.exec);
               changed = true;
             }
             break;
@@ -278,41 +305,31 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
       break;
     }
     // the next event
-    int64_t next = o.horizon;
-    for (int c = 0; c < C; ++c) next = rel[c] < next ? rel[c] : next;
-    for (int i = 0; i < 2 * C; ++i)
-      if (sl[i].state == kHop && sl[i].left < next) next = sl[i].left;
+    int64_t next = next_rel < o.horizon ? next_rel : o.horizon;
+    for (uint64_t m = hopm; m; m &= m - 1) {
+      const int i = __builtin_ctzll(m);
+      next = sl[i].left < next ? sl[i].left : next;
+    }
+    const uint32_t demand = (runm & ~waitm) | (waitm & spinm);
     uint32_t going = 0;  // executors whose CPU piece advances
-    for (int e = 0; e < X; ++e) {
-      if (run[e] < 0 || wait[e]) continue;
-      const uint32_t above = b.hpx_mask[s.x0 + e];
-      bool beaten = false;
-      for (int f = 0; f < X; ++f)
-        if (((above >> f) & 1) && run[f] >= 0 && (!wait[f] || b.spin[s.c0 + (run[f] >> 1)]))
-          beaten = true;
-      if (!beaten) {
-        going |= 1u << e;
-        const int64_t end = t + sl[run[e]].left;
-        next = end < next ? end : next;
-      }
+    for (uint32_t m = runm & ~waitm; m; m &= m - 1) {
+      const int e = __builtin_ctz(m);
+      if (b.hpx_mask[s.x0 + e] & demand) continue;
+      going |= 1u << e;
+      const int64_t end = t + sl[run_slot(run_lo, run_hi, e)].left;
+      next = end < next ? end : next;
     }
     int served[kMaxAccel];
     for (int a = 0; a < NA; ++a) {
-      served[a] = -1;
-      const int nb = b.buckets[s.a0 + a];
-      for (int l = 0; l < nb; ++l)
-        if (cur[a * kDesLevels + l] >= 0) {
-          served[a] = cur[a * kDesLevels + l];
-          break;
-        }
+      const uint32_t lv = (uint32_t)(busy >> (a * kDesLevels)) & 0xff;
+      served[a] = lv ? cur[a * kDesLevels + __builtin_ctz(lv)] : -1;
       if (served[a] >= 0) {
         const int64_t end = t + sl[served[a]].rleft;
         next = end < next ? end : next;
       }
     }
     const int64_t dt = next - t;
-    for (int e = 0; e < X; ++e)
-      if ((going >> e) & 1) sl[run[e]].left -= dt;
+    for (uint32_t m = going; m; m &= m - 1) sl[run_slot(run_lo, run_hi, __builtin_ctz(m))].left -= dt;
     for (int a = 0; a < NA; ++a)
       if (served[a] >= 0) sl[served[a]].rleft -= dt;
     t = next;

@@ -11,6 +11,9 @@ process sees a known sequence of launches:
 * ``train``  - targets, then training steps of the ranking network
 * ``large``  - sets of 256 chains: the uploaded order's analysis, scores of
   1,024 candidate orders per set, the exact confirmation of the top 32
+* ``des``    - the simulation of the study's 8-chain sets, 64 scenarios each
+  (synchronous release, then random offsets), horizon twice the longest period
+* ``units``  - binding of the sweep sets' segments to 4 units per accelerator
 """
 from __future__ import annotations
 
@@ -24,7 +27,8 @@ def main(argv=None):
     from . import _paam, chaingen, surrogate
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("run", choices=("sweep", "search", "score", "guided", "train", "large"))
+    ap.add_argument("run", choices=("sweep", "search", "score", "guided", "train", "large", "des",
+                                    "units"))
     ap.add_argument("--sets", type=int, default=100_000)
     ap.add_argument("--cand", type=int, default=256)
     ap.add_argument("--util", type=int, default=1000)
@@ -46,6 +50,26 @@ def main(argv=None):
         dev = _paam.Chainset(cs, device="cuda:0")
         for u in chaingen.SWEEP_LEVELS[:: max(1, 18 // max(args.repeat, 1))]:
             timed("sweep level %d" % u, lambda: _paam.wcrt(dev, full=True, util_permille=u))
+        return
+    if args.run == "des":
+        cs = chaingen.generate(chaingen.study_params(8, 1, 1), args.sets)
+        dev = _paam.Chainset(cs, device="cuda:0")
+        n_scen, horizon = 64, int(2 * cs.T.max())
+        offs = torch.as_tensor(chaingen.release_offsets(cs, n_scen, 2404)).cuda()
+        obs = torch.empty(cs.n_chains * n_scen, dtype=torch.int64, device="cuda:0")
+        st = torch.empty(cs.n_sets * n_scen, dtype=torch.int8, device="cuda:0")
+        for r in range(args.repeat):
+            o = _paam.des_opts(n_scen, horizon, exec_permille=1000 if r % 2 == 0 else 500, seed=7)
+            timed("simulation %d" % r, lambda: _paam.paam_des_batch(dev, o, offs, obs, st))
+        print("scenarios %d, completed %d" % (cs.n_sets * n_scen, int((st == 0).sum())), flush=True)
+        return
+    if args.run == "units":
+        import numpy as np
+        cs = chaingen.generate("sweep", args.sets)
+        units = np.full(int(cs.set_accel_off[-1]), 4, np.int16)
+        dev = _paam.Chainset(cs, device="cuda:0", units=units, unit_group=_paam.PAAM_UNITS_CHAIN)
+        for r in range(args.repeat):
+            timed("binding %d" % r, lambda: dev.assign_units())
         return
     if args.run == "train":
         cs = chaingen.generate("sweep", args.sets)
