@@ -88,18 +88,27 @@ class Trainer:
         return res
 
     def fit(self, pairs, target, epochs: int, lr: float, order_seed: int, log=None,
-            lr_final: float | None = None):
+            lr_final: float | None = None, start_epoch: int = 0, stop_epoch: int | None = None,
+            checkpoint: str | None = None):
         """Epochs over device pairs/targets in a seeded shuffled order; the
         learning rate decays linearly to lr_final.  Returns the mean loss of
-        every epoch."""
+        every epoch run.
+
+        start_epoch > 0 resumes a run whose first start_epoch epochs are
+        already in the network (restored by load_checkpoint): the epoch
+        orders and the learning-rate schedule continue where they stopped, so
+        the result equals the uninterrupted run; stop_epoch ends a run early
+        (the schedule still spans all epochs).  checkpoint: a path written
+        after every epoch."""
         import torch
 
         from . import chaingen
         n = int(pairs.shape[0])
+        per_epoch = sum(1 for i in range(0, n, self.batch) if min(self.batch, n - i) >= 2)
         steps = epochs * ((n + self.batch - 1) // self.batch)
-        k = 0
+        k = start_epoch * per_epoch
         losses = []
-        for ep in range(epochs):
+        for ep in range(start_epoch, epochs if stop_epoch is None else min(stop_epoch, epochs)):
             perm = torch.from_numpy(chaingen.shuffle_order(n, order_seed + ep)).to(pairs.device)
             acc = torch.zeros(1, dtype=torch.float64, device=pairs.device)
             t0 = time.perf_counter()
@@ -114,9 +123,65 @@ class Trainer:
                 nb += 1
                 k += 1
             losses.append(float(acc.item()) / max(nb, 1))
+            if checkpoint:
+                save_checkpoint(checkpoint, self.net, epoch=ep + 1)
             if log:
                 log("epoch %d: loss %.5f (%.1f s)" % (ep, losses[-1], time.perf_counter() - t0))
         return losses
+
+
+CHECKPOINT_FORMAT = "paam-ranking-network-1"
+
+
+def save_state(path: str, params, m, v, step: int, epoch: int | None = None) -> None:
+    """Writes a training state (float32 master parameters, Adam moments, Adam
+    step, epochs done) as a safetensors file."""
+    from safetensors.numpy import save_file
+    arrays = {k: np.ascontiguousarray(a, np.float32) for k, a in
+              (("params", params), ("adam_m", m), ("adam_v", v))}
+    for k, a in arrays.items():
+        if a.shape != (_paam.MLP_PARAMS,):
+            raise ValueError("%s has shape %s, expected (%d,)" % (k, a.shape, _paam.MLP_PARAMS))
+    meta = {"format": CHECKPOINT_FORMAT, "step": str(int(step)),
+            "epoch": "" if epoch is None else str(int(epoch))}
+    tmp = path + ".tmp"
+    save_file(arrays, tmp, metadata=meta)
+    import os
+    os.replace(tmp, path)
+
+
+def load_state(path: str) -> dict:
+    """Reads a file written by save_state (safetensors: no code runs on load)."""
+    from safetensors import safe_open
+    with safe_open(path, framework="numpy") as f:
+        meta = f.metadata() or {}
+        if meta.get("format") != CHECKPOINT_FORMAT:
+            raise ValueError("%s is not a ranking-network checkpoint" % path)
+        out = {k: f.get_tensor(k) for k in ("params", "adam_m", "adam_v")}
+    for k, a in out.items():
+        if a.dtype != np.float32 or a.shape != (_paam.MLP_PARAMS,):
+            raise ValueError("%s: %s has dtype %s shape %s" % (path, k, a.dtype, a.shape))
+    out["step"] = int(meta["step"])
+    out["epoch"] = int(meta["epoch"]) if meta.get("epoch") else None
+    return out
+
+
+def save_checkpoint(path: str, net: _paam.Network, epoch: int | None = None) -> None:
+    """Checkpoint of a device network: master weights, moments, step."""
+    save_state(path, net.params.cpu().numpy(), net.m.cpu().numpy(), net.v.cpu().numpy(),
+               net.step, epoch)
+
+
+def load_checkpoint(path: str, device="cuda:0", stream=None):
+    """A device network restored from a checkpoint (its bfloat16 copy repacked
+    by the library), and the epochs it holds."""
+    import torch
+    st = load_state(path)
+    net = _paam.Network(st["params"], device=device, stream=stream)
+    net.m.copy_(torch.from_numpy(st["adam_m"]))
+    net.v.copy_(torch.from_numpy(st["adam_v"]))
+    net.step = st["step"]
+    return net, st["epoch"]
 
 
 def spearman(a, b) -> float:
