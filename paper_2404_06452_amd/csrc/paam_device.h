@@ -34,28 +34,44 @@ __device__ __forceinline__ int32_t swap_positions(uint64_t seed, int64_t set, in
 
 // Advances a candidate order from candidate k_from to k_to >= k_from:
 // order[r] = chain at rank r, rank[c] = rank of chain c.  The lanes compute
-// the swap positions of 64 steps at a time into buf[64]; lane 0 applies them
-// in order.  Called by all lanes; ends synchronised.
+// the swap positions of 64 steps at a time; every lane then follows the
+// positions of its own chains (lane, lane + 64, ...: up to 256 per pass)
+// through those swaps, reading each swap from a register of the lane that
+// computed it, and finally writes their ranks and the order.  Called by all
+// lanes; ends synchronised.  buf is unused (kept for the callers' layout).
 __device__ inline void walk_order(int32_t *order, int16_t *rank, int C, uint64_t seed, int64_t set,
                                   int64_t k_from, int64_t k_to, int32_t *buf) {
+  (void)buf;
   if (C < 2 || k_to <= k_from) return;
-  for (int64_t q0 = k_from + 1; q0 <= k_to; q0 += 64) {
-    const int64_t q = q0 + threadIdx.x;
-    if (q <= k_to) buf[threadIdx.x] = swap_positions(seed, set, q, C);
-    __syncthreads();
-    if (threadIdx.x == 0) {
+  const int lane = threadIdx.x;
+  for (int cb = 0; cb < C; cb += 4 * 64) {
+    int pos[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = cb + lane + 64 * j;
+      pos[j] = c < C ? rank[c] : -1;
+    }
+    for (int64_t q0 = k_from + 1; q0 <= k_to; q0 += 64) {
+      const int64_t q = q0 + lane;
+      const int32_t sw = q <= k_to ? swap_positions(seed, set, q, C) : 0;
       const int n = (int)((k_to - q0 + 1) < 64 ? (k_to - q0 + 1) : 64);
       for (int t = 0; t < n; ++t) {
-        const int pa = buf[t] & 0xffff, pb = buf[t] >> 16;
-        const int ca = order[pa], cb = order[pb];
-        order[pa] = cb;
-        order[pb] = ca;
-        rank[cb] = (int16_t)pa;
-        rank[ca] = (int16_t)pb;
+        const int32_t st = __builtin_amdgcn_readlane(sw, t);
+        const int pa = st & 0xffff, pb = st >> 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pos[j] = pos[j] == pa ? pb : (pos[j] == pb ? pa : pos[j]);
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = cb + lane + 64 * j;
+      if (c < C) {
+        rank[c] = (int16_t)pos[j];
+        order[pos[j]] = c;
+      }
+    }
   }
+  __syncthreads();
 }
 
 // float -> bfloat16 bit pattern, round to nearest, ties to even (finite input).

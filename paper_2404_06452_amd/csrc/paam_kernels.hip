@@ -1625,17 +1625,36 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
     if (L.o.guided) {
       const float *sc = L.o.d_scores + set * (int64_t)n_cand;
       const int K = L.o.top_k < n_cand ? L.o.top_k : n_cand;
-      // the K smallest keys, in increasing order
+      // the K smallest keys, in increasing order; up to 1,024 candidates the
+      // keys are read once into registers (16 per lane)
       uint64_t prev = 0;
-      for (int t = 0; t < K; ++t) {
-        uint64_t best = ~0ull;
-        for (int k = threadIdx.x; k < n_cand; k += kWave) {
-          const uint64_t key = score_key(sc[k], k);
-          if ((t == 0 || key > prev) && key < best) best = key;
+      if (n_cand <= 16 * kWave) {
+        uint64_t keys[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int k = threadIdx.x + kWave * j;
+          keys[j] = k < n_cand ? score_key(sc[k], k) : ~0ull;
         }
-        best = wave_min_u64(best);
-        if (threadIdx.x == 0) q.sel[t] = (int32_t)(uint32_t)best;
-        prev = best;
+        for (int t = 0; t < K; ++t) {
+          uint64_t best = ~0ull;
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if ((t == 0 || keys[j] > prev) && keys[j] < best) best = keys[j];
+          best = wave_min_u64(best);
+          if (threadIdx.x == 0) q.sel[t] = (int32_t)(uint32_t)best;
+          prev = best;
+        }
+      } else {
+        for (int t = 0; t < K; ++t) {
+          uint64_t best = ~0ull;
+          for (int k = threadIdx.x; k < n_cand; k += kWave) {
+            const uint64_t key = score_key(sc[k], k);
+            if ((t == 0 || key > prev) && key < best) best = key;
+          }
+          best = wave_min_u64(best);
+          if (threadIdx.x == 0) q.sel[t] = (int32_t)(uint32_t)best;
+          prev = best;
+        }
       }
       __syncthreads();
       for (int t = 0; t < K; ++t) {
