@@ -996,6 +996,16 @@ __device__ __forceinline__ bf16x8 zero8() {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+// Sum of a value over the four 16-lane groups of a wave (lanes l, l^16,
+// l^32, l^48): ds_swizzle exchanges the two halves of each 32-lane half, and
+// v_permlane32_swap exchanges the two 32-lane halves.
+__device__ __forceinline__ float sum_lane_groups(float v) {
+  v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+  const int iv = __float_as_int(v);
+  const auto r = __builtin_amdgcn_permlane32_swap(iv, iv, false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
 // 8 features k0..k0+7 of a row (zero past the 48 features or past the rows);
 // rows are 96 bytes apart, so 16-byte aligned when the buffer is.
 __device__ __forceinline__ bf16x8 load_x8(const uint16_t *row, int k0, bool valid) {
@@ -1048,9 +1058,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
       t0 = load_x8(X + (size_t)r * NF, 8 * lg, rv);
       t1 = load_x8(X + (size_t)r * NF, 32 + 8 * lg, rv);
     };
+    // The MFMA accumulator starts at the bias, so a tile's outputs are the
+    // pre-activations themselves.  Rows past a candidate's chains hold zero
+    // features, so their pre-activation is exactly the bias: every row of a
+    // tile is summed through the ReLU without a per-element mask, and
+    // (rows in the tiles - chains) * ReLU(bias) is taken off once per column.
     // every candidate of the wave within one 16-row tile (sets of up to 16
-    // chains): four candidates share each W1 fragment read from LDS, and a
-    // candidate's pooled sums come straight from its tile
+    // chains): four candidates share each W1 fragment read from LDS
     if (!__any(l < 16 && myrows > 16)) {
       for (int m0 = 0; m0 < 16; m0 += 4) {
         bf16x8 a[4][2];
@@ -1059,25 +1073,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
           rows[j] = __shfl(myrows, m0 + j);
           load_tile(m0 + j, 0, a[j][0], a[j][1]);
         }
+        float pad[4], inv[4];
+        for (int j = 0; j < 4; ++j) {
+          pad[j] = (float)(16 - rows[j]);
+          inv[j] = rows[j] > 0 ? 1.0f / (float)rows[j] : 0.0f;
+        }
+#pragma unroll 4
         for (int nt = 0; nt < 16; ++nt) {
           const int n = nt * 16 + li;
           const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
           const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
-          const float bias = bias1[nt];
+          const float bias = bias1[nt], rb = fmaxf(bias, 0.0f);
           for (int j = 0; j < 4; ++j) {
-            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            f32x4 acc = {bias, bias, bias, bias};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][0], bb0, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][1], bb1, acc, 0, 0, 0);
-            float sacc = 0.0f;
-            for (int i = 0; i < 4; ++i) {
-              const int rr = 4 * lg + i;
-              const float z = acc[i] + bias;
-              sacc += (rr < rows[j] && z > 0.0f) ? z : 0.0f;
-            }
-            float sv = 0.0f + sacc;
-            sv += __shfl_xor(sv, 16);
-            sv += __shfl_xor(sv, 32);
-            const float pv = rows[j] > 0 ? sv / (float)rows[j] : 0.0f;
+            const float sv = sum_lane_groups((fmaxf(acc[0], 0.0f) + fmaxf(acc[1], 0.0f)) +
+                                             (fmaxf(acc[2], 0.0f) + fmaxf(acc[3], 0.0f)));
+            const float pv = (sv - pad[j] * rb) * inv[j];
             if (lg == 0) Pq[(w * 16 + m0 + j) * kPqStride + nt * 16 + li] = bf16_rne(pv);
           }
         }
@@ -1090,6 +1103,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         const int rows = __shfl(myrows, m);
         float pool[16];
         for (int nt = 0; nt < 16; ++nt) pool[nt] = 0.0f;
+        int tiles = 0;
         for (int r0 = 0;; r0 += 16) {
           const bf16x8 a0 = na0, a1 = na1;
           if (r0 + 16 < rows) {
@@ -1098,29 +1112,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             load_tile(m + 1, 0, na0, na1);
           }
           if (r0 < rows) {
+            ++tiles;
+#pragma unroll 4
             for (int nt = 0; nt < 16; ++nt) {
               const int n = nt * 16 + li;
               const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
               const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
-              f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+              const float bias = bias1[nt];
+              f32x4 acc = {bias, bias, bias, bias};
               acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
               acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
-              float sacc = 0.0f;
-              for (int j = 0; j < 4; ++j) {
-                const int rr = r0 + 4 * lg + j;
-                const float z = acc[j] + bias1[nt];
-                sacc += (rr < rows && z > 0.0f) ? z : 0.0f;
-              }
-              pool[nt] += sacc;
+              pool[nt] += (fmaxf(acc[0], 0.0f) + fmaxf(acc[1], 0.0f)) +
+                          (fmaxf(acc[2], 0.0f) + fmaxf(acc[3], 0.0f));
             }
           }
           if (r0 + 16 >= rows) break;
         }
+        const float pad = (float)(16 * tiles - rows);
+        const float inv = rows > 0 ? 1.0f / (float)rows : 0.0f;
         for (int nt = 0; nt < 16; ++nt) {
-          float sv = pool[nt];
-          sv += __shfl_xor(sv, 16);
-          sv += __shfl_xor(sv, 32);
-          const float p = rows > 0 ? sv / (float)rows : 0.0f;
+          const float sv = sum_lane_groups(pool[nt]);
+          const float p = (sv - pad * fmaxf(bias1[nt], 0.0f)) * inv;
           if (lg == 0) Pq[mb * kPqStride + nt * 16 + li] = bf16_rne(p);
         }
       }
