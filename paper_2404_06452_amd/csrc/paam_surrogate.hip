@@ -996,6 +996,19 @@ __device__ __forceinline__ bf16x8 zero8() {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+// max(x, 0) in one instruction (median of x, 0 and +inf; no NaN arises here).
+__device__ __forceinline__ float relu(float x) {
+  return __builtin_amdgcn_fmed3f(x, 0.0f, __builtin_inff());
+}
+
+// The value held by the lane l ^ 32 (the other 32-lane half), by one
+// v_permlane32_swap of the value with itself.
+__device__ __forceinline__ float other_half(float v) {
+  const int iv = __float_as_int(v);
+  const auto r = __builtin_amdgcn_permlane32_swap(iv, iv, false, false);
+  return __int_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+}
+
 // Sum of a value over the four 16-lane groups of a wave (lanes l, l^16,
 // l^32, l^48): ds_swizzle exchanges the two halves of each 32-lane half, and
 // v_permlane32_swap exchanges the two 32-lane halves.
@@ -1028,6 +1041,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
   __shared__ __attribute__((aligned(16))) uint16_t W1s[NH * KP];
   __shared__ __attribute__((aligned(16))) uint16_t Pq[kFwdBlock * kPqStride];
   __shared__ float ysum[4][kFwdBlock];
+  __shared__ float b1s[NH];
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int li = l & 15, lg = l >> 4;
@@ -1040,6 +1054,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
   }
   float bias1[16];
   for (int nt = 0; nt < 16; ++nt) bias1[nt] = b1[nt * 16 + li];
+  for (int i = tid; i < NH; i += 256) b1s[i] = b1[i];
   const int64_t nblocks = (L.n + kFwdBlock - 1) / kFwdBlock;
   __syncthreads();
   for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
@@ -1068,31 +1083,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     if (!__any(l < 16 && myrows > 16)) {
       for (int m0 = 0; m0 < 16; m0 += 4) {
         bf16x8 a[4][2];
-        int rows[4];
-        for (int j = 0; j < 4; ++j) {
-          rows[j] = __shfl(myrows, m0 + j);
-          load_tile(m0 + j, 0, a[j][0], a[j][1]);
-        }
-        float pad[4], inv[4];
-        for (int j = 0; j < 4; ++j) {
-          pad[j] = (float)(16 - rows[j]);
-          inv[j] = rows[j] > 0 ? 1.0f / (float)rows[j] : 0.0f;
-        }
-#pragma unroll 4
+        for (int j = 0; j < 4; ++j) load_tile(m0 + j, 0, a[j][0], a[j][1]);
+        // lane group lg ends up with the sums of candidate m0 + lg
+        const int rows = __shfl(myrows, m0 + lg);
+        const float pad = (float)(16 - rows);
+        const float inv = rows > 0 ? 1.0f / (float)rows : 0.0f;
+        uint16_t *dst = Pq + (w * 16 + m0 + lg) * kPqStride + li;
+#pragma unroll 2
         for (int nt = 0; nt < 16; ++nt) {
           const int n = nt * 16 + li;
           const bf16x8 bb0 = load8(W1s + n * KP + 8 * lg);
           const bf16x8 bb1 = load8(W1s + n * KP + 32 + 8 * lg);
-          const float bias = bias1[nt], rb = fmaxf(bias, 0.0f);
+          const float bias = b1s[nt * 16 + li];
+          f32x4 acc[4];
           for (int j = 0; j < 4; ++j) {
-            f32x4 acc = {bias, bias, bias, bias};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][0], bb0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][1], bb1, acc, 0, 0, 0);
-            const float sv = sum_lane_groups((fmaxf(acc[0], 0.0f) + fmaxf(acc[1], 0.0f)) +
-                                             (fmaxf(acc[2], 0.0f) + fmaxf(acc[3], 0.0f)));
-            const float pv = (sv - pad[j] * rb) * inv[j];
-            if (lg == 0) Pq[(w * 16 + m0 + j) * kPqStride + nt * 16 + li] = bf16_rne(pv);
+            acc[j] = f32x4{bias, bias, bias, bias};
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][0], bb0, acc[j], 0, 0, 0);
           }
+          for (int j = 0; j < 4; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][1], bb1, acc[j], 0, 0, 0);
+          float v[4];
+          for (int j = 0; j < 4; ++j)
+            v[j] = (relu(acc[j][0]) + relu(acc[j][1])) + (relu(acc[j][2]) + relu(acc[j][3]));
+          // 4 x 4 transpose-and-add over the lane groups: first between lane
+          // groups lg and lg ^ 1 (candidates of parity lg & 1 stay), then
+          // between lg and lg ^ 2 (candidate lg stays)
+          const bool odd = (lg & 1) != 0;
+          const float s0 = odd ? v[0] : v[1], s1 = odd ? v[2] : v[3];
+          const float r0 = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(s0), 0x401F));
+          const float r1 = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(s1), 0x401F));
+          const float x = (odd ? v[1] : v[0]) + r0;  // candidate lg & 1
+          const float y = (odd ? v[3] : v[2]) + r1;  // candidate (lg & 1) + 2
+          const bool up = (lg & 2) != 0;
+          const float tot = (up ? y : x) + other_half(up ? x : y);
+          dst[nt * 16] = bf16_rne((tot - pad * relu(bias)) * inv);
         }
       }
     } else {
@@ -1122,8 +1146,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
               f32x4 acc = {bias, bias, bias, bias};
               acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb0, acc, 0, 0, 0);
               acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb1, acc, 0, 0, 0);
-              pool[nt] += (fmaxf(acc[0], 0.0f) + fmaxf(acc[1], 0.0f)) +
-                          (fmaxf(acc[2], 0.0f) + fmaxf(acc[3], 0.0f));
+              pool[nt] += (relu(acc[0]) + relu(acc[1])) + (relu(acc[2]) + relu(acc[3]));
             }
           }
           if (r0 + 16 >= rows) break;
@@ -1132,7 +1155,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         const float inv = rows > 0 ? 1.0f / (float)rows : 0.0f;
         for (int nt = 0; nt < 16; ++nt) {
           const float sv = sum_lane_groups(pool[nt]);
-          const float p = (sv - pad * fmaxf(bias1[nt], 0.0f)) * inv;
+          const float p = (sv - pad * relu(bias1[nt])) * inv;
           if (lg == 0) Pq[mb * kPqStride + nt * 16 + li] = bf16_rne(p);
         }
       }
