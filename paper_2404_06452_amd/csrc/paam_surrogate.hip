@@ -996,9 +996,10 @@ __device__ __forceinline__ bf16x8 zero8() {
   return __builtin_bit_cast(bf16x8, v);
 }
 
-// max(x, 0) in one instruction (median of x, 0 and +inf; no NaN arises here).
+// max(x, 0) for finite x in one instruction: the median of x, 0 and the
+// largest finite float (fmaxf would add a NaN-quieting instruction).
 __device__ __forceinline__ float relu(float x) {
-  return __builtin_amdgcn_fmed3f(x, 0.0f, __builtin_inff());
+  return __builtin_amdgcn_fmed3f(x, 0.0f, 3.4028234663852886e38f);
 }
 
 // The value held by the lane l ^ 32 (the other 32-lane half), by one
