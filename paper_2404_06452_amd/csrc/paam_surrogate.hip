@@ -1082,9 +1082,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     // every candidate of the wave within one 16-row tile (sets of up to 16
     // chains): four candidates share each W1 fragment read from LDS
     if (!__any(l < 16 && myrows > 16)) {
+      // the tiles of the next four candidates load during this group's work
+      bf16x8 nx[4][2];
+      for (int j = 0; j < 4; ++j) load_tile(j, 0, nx[j][0], nx[j][1]);
       for (int m0 = 0; m0 < 16; m0 += 4) {
         bf16x8 a[4][2];
-        for (int j = 0; j < 4; ++j) load_tile(m0 + j, 0, a[j][0], a[j][1]);
+        for (int j = 0; j < 4; ++j) {
+          a[j][0] = nx[j][0];
+          a[j][1] = nx[j][1];
+        }
+        if (m0 + 4 < 16)
+          for (int j = 0; j < 4; ++j) load_tile(m0 + 4 + j, 0, nx[j][0], nx[j][1]);
         // lane group lg ends up with the sums of candidate m0 + lg
         const int rows = __shfl(myrows, m0 + lg);
         const float pad = (float)(16 - rows);
