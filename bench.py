@@ -45,8 +45,8 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "d4ba8510aa35ab11c3f56d3a0dbb9de14da2f483af9b6bfafc22df6a05c7be53",
-           "bytes_per_launch": 16.02e9, "sets": 1_000_000, "waves_per_cu": 20}
+TRAFFIC = {"sha256": "3be20b63f01e6e32f4f142f8f54523a5cabef782d5fca9841394a47e94c7bc85",
+           "bytes_per_launch": 16.05e9, "sets": 1_000_000, "waves_per_cu": 20}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
