@@ -1258,11 +1258,16 @@ __global__ __launch_bounds__(256) void backward_kernel(BwdLaunch L) {
     }
   }
   __syncthreads();
-  // dW2[j][k] = sum_m dz2[m][j] * pq[m][k]
-  for (int k = 0; k < NH; ++k) {
-    float s = 0.0f;
-    for (int m = 0; m < nc; ++m) s += dz2[m][j] * pq[m][k];
-    part[OW2 + j * NH + k] = s;
+  // dW2[i][j] = sum_m dz2[m][i] * pq[m][j]: thread j owns column j, so the
+  // stores of every row are coalesced across the threads
+  {
+    float pqj[kBwdChunk];
+    for (int m = 0; m < kBwdChunk; ++m) pqj[m] = m < nc ? pq[m][j] : 0.0f;
+    for (int i = 0; i < NH; ++i) {
+      float s = 0.0f;
+      for (int m = 0; m < nc; ++m) s += dz2[m][i] * pqj[m];
+      part[OW2 + i * NH + j] = s;
+    }
   }
   // dp[m][k = j] = sum_i dz2[m][i] * W2[i][j]
   for (int m = 0; m < nc; ++m) {
