@@ -511,6 +511,16 @@ __device__ void feat_inversions(const FeatTables &t, int C, int pa, int pb, bool
 // suffix maxima and counts, the same-bucket blocking term from a suffix
 // maximum segmented by bucket level.  Candidate g's rows start at
 // rows + g * row_stride * 48.
+// A 64-bit value moved by a DPP row shift (16-lane rows; 0 where the source
+// lies outside the row): row_shr:n (0x110 + n) takes lane i - n, row_shl:n
+// (0x100 + n) lane i + n.
+template <int Ctrl>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, Ctrl, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), Ctrl, 0xf, 0xf, true);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables &t, int C,
                                 int ng, uint16_t *rows, int row_stride) {
   const int lane = threadIdx.x;
@@ -522,7 +532,19 @@ __device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables
   const bool ok = g < ng;
   const int c = ok ? t.ordg[g * C + r] : 0;
   const uint32_t uses = ok ? (uint32_t)t.uses[c] : 0u;
+  // Sets of exactly 16 chains: every candidate of a pass is one 16-lane row,
+  // so the scans below run on DPP row shifts instead of LDS-routed shuffles
+  // (the sums and maxima take 0 from outside the row; every scanned value is
+  // non-negative).
+  const bool rowwise = C == 16;
   auto sum_up = [&](int64_t v) {
+    if (rowwise) {
+      v += dpp64<0x111>(v);
+      v += dpp64<0x112>(v);
+      v += dpp64<0x114>(v);
+      v += dpp64<0x118>(v);
+      return v;
+    }
     for (int o = 1; o < C; o <<= 1) {
       const int64_t n = __shfl_up(v, o);
       if (r >= o) v += n;
@@ -530,6 +552,13 @@ __device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables
     return v;
   };
   auto sum_down = [&](int64_t v) {
+    if (rowwise) {
+      v += dpp64<0x101>(v);
+      v += dpp64<0x102>(v);
+      v += dpp64<0x104>(v);
+      v += dpp64<0x108>(v);
+      return v;
+    }
     for (int o = 1; o < C; o <<= 1) {
       const int64_t n = __shfl_down(v, o);
       if (r + o < C) v += n;
@@ -537,6 +566,17 @@ __device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables
     return v;
   };
   auto max_down = [&](int64_t v) {
+    if (rowwise) {
+      int64_t n = dpp64<0x101>(v);
+      v = n > v ? n : v;
+      n = dpp64<0x102>(v);
+      v = n > v ? n : v;
+      n = dpp64<0x104>(v);
+      v = n > v ? n : v;
+      n = dpp64<0x108>(v);
+      v = n > v ? n : v;
+      return v;
+    }
     for (int o = 1; o < C; o <<= 1) {
       const int64_t n = __shfl_down(v, o);
       if (r + o < C) v = n > v ? n : v;
@@ -545,6 +585,7 @@ __device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables
   };
   // the value of the next rank of the same candidate, 0 past the last
   auto next = [&](int64_t v) {
+    if (rowwise) return dpp64<0x101>(v);
     const int64_t n = __shfl_down(v, 1);
     return r + 1 < C ? n : (int64_t)0;
   };
