@@ -640,12 +640,29 @@ __device__ void feat_group_scan(const DevBatch &b, int64_t set, const FeatTables
     const int64_t nb = b.buckets[a0 + a];
     const int64_t key = (uab * nb) / m;    // bucket level of rank r
     int64_t xv = vmax;
-    for (int o = 1; o < C; o <<= 1) {
-      const int64_t nv = __shfl_down(xv, o);
-      const int64_t nk = __shfl_down(key, o);
-      if (r + o < C && nk == key) xv = nv > xv ? nv : xv;
+    if (rowwise) {
+      // the same segmented maximum on DPP row shifts (r + o < 16 keeps the
+      // comparison inside the candidate's row)
+      int64_t nv = dpp64<0x101>(xv), nk = dpp64<0x101>(key);
+      if (r + 1 < C && nk == key) xv = nv > xv ? nv : xv;
+      nv = dpp64<0x102>(xv);
+      nk = dpp64<0x102>(key);
+      if (r + 2 < C && nk == key) xv = nv > xv ? nv : xv;
+      nv = dpp64<0x104>(xv);
+      nk = dpp64<0x104>(key);
+      if (r + 4 < C && nk == key) xv = nv > xv ? nv : xv;
+      nv = dpp64<0x108>(xv);
+      nk = dpp64<0x108>(key);
+      if (r + 8 < C && nk == key) xv = nv > xv ? nv : xv;
+    } else {
+      for (int o = 1; o < C; o <<= 1) {
+        const int64_t nv = __shfl_down(xv, o);
+        const int64_t nk = __shfl_down(key, o);
+        if (r + o < C && nk == key) xv = nv > xv ? nv : xv;
+      }
     }
-    const int64_t nv1 = __shfl_down(xv, 1), nk1 = __shfl_down(key, 1);
+    const int64_t nv1 = rowwise ? dpp64<0x101>(xv) : __shfl_down(xv, 1);
+    const int64_t nk1 = rowwise ? dpp64<0x101>(key) : __shfl_down(key, 1);
     if ((uses >> a) & 1u) {
       n_acc += 2 * (int64_t)t.nra[c * NAm + a] * hpA;
       q33 += pqA;
