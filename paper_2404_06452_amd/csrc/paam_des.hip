@@ -59,6 +59,8 @@ struct Slot {
 struct Sim {
   const DevBatch *b;
   const paam_des_opts *o;
+  const int16_t *rank;  // [C] priority rank of every chain (LDS)
+  const int8_t *lev;    // [C][kMaxAccel] bucket level of a chain's requests (LDS)
   int64_t set, scen, c0, a0, x0, j0;
   int n_cb;
   int C, X, NA;
@@ -82,20 +84,6 @@ __device__ int64_t actual(const Sim &s, int c, int32_t job, int cbl, int item, i
   return W - (int64_t)(k % (uint64_t)(W - lo + 1));
 }
 
-// Bucket level of chain c on accelerator a: chains with a segment on a,
-// ranked by priority, rank r of m on level floor(r n / m).
-__device__ int level_of(const Sim &s, const uint8_t *amask, int c, int a) {
-  const DevBatch &b = *s.b;
-  const int rc = b.rank0[s.c0 + c];
-  int m = 0, r = 0;
-  for (int d = 0; d < s.C; ++d)
-    if ((amask[d] >> a) & 1) {
-      ++m;
-      r += b.rank0[s.c0 + d] < rc;
-    }
-  return (int)((int64_t)r * b.buckets[s.a0 + a] / m);
-}
-
 // Slot sets, executor sets and occupied bucket levels are bit masks held in
 // registers, so the per-instant scans touch only the slots that matter (the
 // ready, travelling or queued ones); the per-slot fields live in private
@@ -117,7 +105,6 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
   Slot sl[kSlots];
   int64_t rel[kDesChains], worst[kDesChains];
   int32_t njob[kDesChains];
-  uint8_t amask[kDesChains];
   int8_t cur[kMaxAccel * kDesLevels];
   uint64_t live = 0, ready = 0, hopm = 0, queued = 0, busy = 0;  // slots; levels a*8+l
   uint32_t runm = 0, waitm = 0, spinm = 0;                         // executors
@@ -128,11 +115,6 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
     next_rel = rel[c] < next_rel ? rel[c] : next_rel;
     worst[c] = -1;
     njob[c] = 0;
-    amask[c] = 0;
-  }
-  {
-    const int64_t gs = b.set_seg_off[s.set], ge = b.set_seg_off[s.set + 1];
-    for (int64_t g = gs; g < ge; ++g) amask[b.seg_chain[g]] |= (uint8_t)(1u << b.seg_accel[g]);
   }
   int32_t seq = 0;
   int64_t t = 0, steps = 0;
@@ -183,7 +165,7 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
           for (uint64_t m = ready; m; m &= m - 1) {
             const int i = __builtin_ctzll(m);
             if (sl[i].exec != e) continue;
-            const int ri = b.rank0[s.c0 + (i >> 1)];
+            const int ri = s.rank[i >> 1];
             if (best < 0 || ri < brank || (ri == brank && sl[i].release < sl[best].release)) {
               best = i;
               brank = ri;
@@ -238,7 +220,7 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
                 const int a = b.seg_accel[g0 + k];
                 queued |= 1ull << i;
                 x.ra = (int8_t)a;
-                x.rl = (int8_t)level_of(s, amask, c, a);
+                x.rl = s.lev[c * kMaxAccel + a];
                 x.rleft = actual(s, c, x.job, cbl, k, scaled(s, b.A[g0 + k])) + 2 * b.akappa[s.a0 + a];
                 x.seq = seq++;
                 x.left = -2;
@@ -273,7 +255,7 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
             for (uint64_t m = queued; m; m &= m - 1) {
               const int i = __builtin_ctzll(m);
               if (sl[i].ra != a || sl[i].rl != l) continue;
-              const int ri = b.rank0[s.c0 + (i >> 1)];
+              const int ri = s.rank[i >> 1];
               if (best < 0 || ri < brank || (ri == brank && sl[i].seq < sl[best].seq)) {
                 best = i;
                 brank = ri;
@@ -340,13 +322,16 @@ done:
 }
 
 __global__ __launch_bounds__(kWave) void des_kernel(DesLaunch L) {
+  __shared__ int16_t rank_s[kDesChains];
+  __shared__ int32_t amask_s[kDesChains];
+  __shared__ int8_t lev_s[kDesChains * kMaxAccel];
   const DevBatch &b = L.b;
+  const int lane = threadIdx.x;
   const int64_t per_set = (L.o.n_scen + kWave - 1) / kWave;
   const int64_t n_work = b.n_sets * per_set;
   for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
     const int64_t set = w / per_set;
-    const int64_t scen = (w % per_set) * kWave + threadIdx.x;
-    if (scen >= L.o.n_scen) continue;
+    const int64_t scen = (w % per_set) * kWave + lane;
     Sim s;
     s.b = &b;
     s.o = &L.o;
@@ -360,8 +345,37 @@ __global__ __launch_bounds__(kWave) void des_kernel(DesLaunch L) {
     s.NA = (int)(b.set_accel_off[set + 1] - s.a0);
     s.j0 = b.set_cb_off[set];
     s.n_cb = (int)(b.set_cb_off[set + 1] - s.j0);
-    const int64_t base = s.c0 * L.o.n_scen + scen * s.C;
-    simulate(s, L.offsets + base, L.obs + base, L.status + set * L.o.n_scen + scen);
+    // the set's tables, shared by the wave's scenarios: ranks, accelerators
+    // used by every chain, and the bucket level of every (chain, accelerator)
+    // user (Sec. IV-C: users ranked by priority, rank r of m on level
+    // floor(r * n / m))
+    for (int c = lane; c < s.C; c += kWave) {
+      rank_s[c] = b.rank0[s.c0 + c];
+      amask_s[c] = 0;
+    }
+    __syncthreads();
+    for (int64_t g = b.set_seg_off[set] + lane; g < b.set_seg_off[set + 1]; g += kWave)
+      atomicOr(&amask_s[b.seg_chain[g]], 1 << b.seg_accel[g]);
+    __syncthreads();
+    for (int i = lane; i < s.C * s.NA; i += kWave) {
+      const int c = i / s.NA, a = i - c * s.NA;
+      int m = 0, r = 0;
+      for (int d = 0; d < s.C; ++d)
+        if ((amask_s[d] >> a) & 1) {
+          ++m;
+          r += rank_s[d] < rank_s[c];
+        }
+      lev_s[c * kMaxAccel + a] =
+          ((amask_s[c] >> a) & 1) ? (int8_t)((int64_t)r * b.buckets[s.a0 + a] / m) : (int8_t)-1;
+    }
+    __syncthreads();
+    s.rank = rank_s;
+    s.lev = lev_s;
+    if (scen < L.o.n_scen) {
+      const int64_t base = s.c0 * L.o.n_scen + scen * s.C;
+      simulate(s, L.offsets + base, L.obs + base, L.status + set * L.o.n_scen + scen);
+    }
+    __syncthreads();
   }
 }
 
