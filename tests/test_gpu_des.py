@@ -105,3 +105,26 @@ def test_des_rejects_sets_beyond_its_limits():
     with pytest.raises(_paam.PaamError):
         _paam.simulate(dev, np.zeros(cs.n_chains, np.int64), 1, 1 << 41)
     dev.free()
+
+
+@pytest.mark.gpu
+def test_des_at_its_limits():
+    """32 chains, 16 executors (pairs sharing cores), 8 segments per callback,
+    two accelerators with 8 buckets each: the largest sets the kernel takes."""
+    rng = random.Random(5)
+    sets = []
+    for _ in range(12):
+        X = 16
+        chains = []
+        for c in range(32):
+            T = rng.choice([200, 300, 500, 800, 1000, 2000]) * 1000
+            cbs = [{"E": rng.randint(0, 3000), "exec": rng.randrange(X),
+                    "segs": [[rng.randint(0, 2000), rng.randrange(2)] for _ in range(rng.randint(0, 8))]}
+                   for _ in range(rng.randint(1, 4))]
+            chains.append({"T": T, "D": T, "prio": 100 - c, "spin": rng.randint(0, 1), "cbs": cbs})
+        sets.append({"chains": chains, "exec_core": [e // 2 for e in range(X)],
+                     "exec_prio": [2 - (e % 2) for e in range(X)], "accel_buckets": [8, 8],
+                     "accel_eps": [100, 50], "accel_kappa": [10, 0], "eps_hop": 30})
+    cs = chaingen.from_sets(sets)
+    g, _ = _parity(cs, 64, 6_000_000, "limits", util_permille=200, exec_permille=600, seed=8)
+    assert (g["obs"] >= 0).sum() > 1000

@@ -111,3 +111,15 @@ def test_units_rejected_without_binding():
         dev.assign_units()
     assert np.array_equal(dev.seg_units().cpu().numpy(), cs.accel)
     dev.free()
+
+
+@pytest.mark.gpu
+def test_units_at_their_limits():
+    # 2,000 segments per set (the limit is 2,048) over eight units in all
+    p = chaingen.PRESETS["small"].replace(seed=31, chains=(200, 200), cbs=(10, 10), n_exec=4,
+                                          pseg=(1.0, 1.0), n_accel=2, util=(0.3, 0.3))
+    cs = chaingen.generate(p, 3)
+    assert max(int(cs.cb_seg_off[cs.chain_cb_off[cs.set_chain_off[s + 1]]] -
+                   cs.cb_seg_off[cs.chain_cb_off[cs.set_chain_off[s]]]) for s in range(3)) <= 2048
+    for group in (0, 2):
+        _check(cs, np.array([5, 3] * cs.n_sets, np.int16), group, "2,000 segments, 8 units")
