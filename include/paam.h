@@ -353,7 +353,8 @@ paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opt
  * is W - (r mod (W - floor(W * exec_permille / 1000) + 1)), r from
  * SplitMix64 keyed by (seed, set, scenario, chain, job, callback, item).
  * Limits: 32 chains, 16 executors, 8 segments per callback, 8 buckets per
- * accelerator (PAAM_E_RANGE otherwise). */
+ * accelerator, and 12 bytes per callback plus 9 per segment of a set within
+ * 48 KB (its tables are staged in LDS) -- PAAM_E_RANGE otherwise. */
 typedef struct {
   int32_t n_scen;        /* scenarios per set, 1..2^20 */
   int32_t exec_permille; /* 0..1000 */

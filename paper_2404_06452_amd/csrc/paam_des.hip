@@ -61,6 +61,12 @@ struct Sim {
   const paam_des_opts *o;
   const int16_t *rank;  // [C] priority rank of every chain (LDS)
   const int8_t *lev;    // [C][kMaxAccel] bucket level of a chain's requests (LDS)
+  // the set's tables, staged in LDS once per wave (times already scaled by
+  // util_permille): per callback E, first segment, executor; per segment A
+  // and accelerator
+  const int64_t *cbE, *segA;
+  const int16_t *cbSeg;  // [n_cb + 1] set-local segment offsets
+  const int8_t *cbExec, *segAcc;
   int64_t set, scen, c0, a0, x0, j0;
   int n_cb;
   int C, X, NA;
@@ -139,7 +145,7 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
             x.release = rel[c];
             x.job = k;
             x.cb = b.chain_cb_lo[s.c0 + c];
-            x.exec = b.cb_exec[s.j0 + x.cb];
+            x.exec = s.cbExec[x.cb];
             live |= 1ull << i;
             ready |= 1ull << i;
             rel[c] += b.T[s.c0 + c];
@@ -154,7 +160,7 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
         if (sl[i].left <= t) {
           hopm &= ~(1ull << i);
           ready |= 1ull << i;
-          sl[i].exec = b.cb_exec[s.j0 + sl[i].cb];
+          sl[i].exec = s.cbExec[sl[i].cb];
           changed = true;
         }
       }
@@ -185,8 +191,8 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
           const int i = run_slot(run_lo, run_hi, e);
           Slot &x = sl[i];
           const int c = i >> 1;
-          const int64_t g0 = b.cb_seg_off[s.j0 + x.cb];
-          const int eta = (int)(b.cb_seg_off[s.j0 + x.cb + 1] - g0);
+          const int g0 = s.cbSeg[x.cb];
+          const int eta = s.cbSeg[x.cb + 1] - g0;
           const int cb_lo = b.chain_cb_lo[s.c0 + c];
           const int cb_hi = c + 1 < C ? b.chain_cb_lo[s.c0 + c + 1] : s.n_cb;
           const int cbl = x.cb - cb_lo;
@@ -201,7 +207,7 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
                 live &= ~(1ull << i);
               } else {
                 x.cb += 1;
-                const int nx = b.cb_exec[s.j0 + x.cb];
+                const int nx = s.cbExec[x.cb];
                 if (nx != e && hop > 0) {
                   hopm |= 1ull << i;
                   x.left = t + hop;
@@ -217,11 +223,11 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
             if (ph == 2) {  // an accelerator request
               if (x.left == -1) {
                 const int k = (x.pos - 1) / 3;
-                const int a = b.seg_accel[g0 + k];
+                const int a = s.segAcc[g0 + k];
                 queued |= 1ull << i;
                 x.ra = (int8_t)a;
                 x.rl = s.lev[c * kMaxAccel + a];
-                x.rleft = actual(s, c, x.job, cbl, k, scaled(s, b.A[g0 + k])) + 2 * b.akappa[s.a0 + a];
+                x.rleft = actual(s, c, x.job, cbl, k, s.segA[g0 + k]) + 2 * b.akappa[s.a0 + a];
                 x.seq = seq++;
                 x.left = -2;
                 waitm |= 1u << e;
@@ -231,9 +237,9 @@ __device__ void simulate(const Sim &s, const int64_t *offs, int64_t *obs, int8_t
             }
             if (x.left == -1) {
               if (ph == 1) {
-                x.left = b.aeps[s.a0 + b.seg_accel[g0 + (x.pos - 1) / 3]];
+                x.left = b.aeps[s.a0 + s.segAcc[g0 + (x.pos - 1) / 3]];
               } else {
-                const int64_t E = actual(s, c, x.job, cbl, 63, scaled(s, b.E[s.j0 + x.cb]));
+                const int64_t E = actual(s, c, x.job, cbl, 63, s.cbE[x.cb]);
                 const int p = x.pos / 3, parts = eta + 1;
                 x.left = E / parts + (p < E % parts ? 1 : 0);
               }
@@ -325,7 +331,15 @@ __global__ __launch_bounds__(kWave) void des_kernel(DesLaunch L) {
   __shared__ int16_t rank_s[kDesChains];
   __shared__ int32_t amask_s[kDesChains];
   __shared__ int8_t lev_s[kDesChains * kMaxAccel];
+  extern __shared__ __attribute__((aligned(16))) unsigned char des_lds[];
   const DevBatch &b = L.b;
+  // per set: E and first segment of every callback, A of every segment,
+  // then the byte-wide executors and accelerators (sized for the batch)
+  int64_t *cbE = reinterpret_cast<int64_t *>(des_lds);
+  int64_t *segA = cbE + L.max_cbs;
+  int16_t *cbSeg = reinterpret_cast<int16_t *>(segA + L.max_segs);
+  int8_t *cbExec = reinterpret_cast<int8_t *>(cbSeg + L.max_cbs + 1);
+  int8_t *segAcc = cbExec + L.max_cbs;
   const int lane = threadIdx.x;
   const int64_t per_set = (L.o.n_scen + kWave - 1) / kWave;
   const int64_t n_work = b.n_sets * per_set;
@@ -369,8 +383,28 @@ __global__ __launch_bounds__(kWave) void des_kernel(DesLaunch L) {
           ((amask_s[c] >> a) & 1) ? (int8_t)((int64_t)r * b.buckets[s.a0 + a] / m) : (int8_t)-1;
     }
     __syncthreads();
+    {
+      const int64_t g0 = b.set_seg_off[set];
+      const int nseg = (int)(b.set_seg_off[set + 1] - g0);
+      for (int j = lane; j < s.n_cb; j += kWave) {
+        cbE[j] = scaled(s, b.E[s.j0 + j]);
+        cbSeg[j] = (int16_t)(b.cb_seg_off[s.j0 + j] - g0);
+        cbExec[j] = b.cb_exec[s.j0 + j];
+      }
+      if (lane == 0) cbSeg[s.n_cb] = (int16_t)nseg;
+      for (int g = lane; g < nseg; g += kWave) {
+        segA[g] = scaled(s, b.A[g0 + g]);
+        segAcc[g] = (int8_t)b.seg_accel[g0 + g];
+      }
+    }
+    __syncthreads();
     s.rank = rank_s;
     s.lev = lev_s;
+    s.cbE = cbE;
+    s.segA = segA;
+    s.cbSeg = cbSeg;
+    s.cbExec = cbExec;
+    s.segAcc = segAcc;
     if (scen < L.o.n_scen) {
       const int64_t base = s.c0 * L.o.n_scen + scen * s.C;
       simulate(s, L.offsets + base, L.obs + base, L.status + set * L.o.n_scen + scen);
@@ -381,8 +415,14 @@ __global__ __launch_bounds__(kWave) void des_kernel(DesLaunch L) {
 
 }  // namespace
 
+size_t des_lds_bytes(int64_t max_cbs, int64_t max_segs) {
+  return (size_t)max_cbs * 8 + (size_t)max_segs * 8 + (size_t)(max_cbs + 1) * 2 + (size_t)max_cbs +
+         (size_t)max_segs + 16;
+}
+
 int launch_des(const DesLaunch &L, void *stream) {
-  hipLaunchKernelGGL(des_kernel, dim3(L.grid), dim3(kWave), 0, (hipStream_t)stream, L);
+  hipLaunchKernelGGL(des_kernel, dim3(L.grid), dim3(kWave), des_lds_bytes(L.max_cbs, L.max_segs),
+                     (hipStream_t)stream, L);
   return (int)hipGetLastError();
 }
 

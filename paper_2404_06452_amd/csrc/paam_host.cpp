@@ -78,7 +78,7 @@ struct Plan {
   std::vector<int64_t> set_accel_x;
   int64_t n_types = 0;
   int32_t unit_group = -1;
-  int32_t max_cb_segs = 0, max_buckets = 0;
+  int32_t max_cb_segs = 0, max_buckets = 0, max_set_cbs = 0;
   std::vector<int64_t> work_order;
   int32_t max_C = 0, max_X = 0, max_NA = 0, max_runs = 0, max_segs = 0;
   std::vector<paam::SizeClass> classes;
@@ -360,6 +360,7 @@ paam_status make_plan(const paam_chainset_host *h, Plan &P) {
     P.max_runs = std::max(P.max_runs, nrun[s]);
     P.max_tot = std::max(P.max_tot, tot[s]);
     P.max_segs = std::max(P.max_segs, (int32_t)(h->cb_seg_off[cb1] - h->cb_seg_off[cb0]));
+    P.max_set_cbs = std::max(P.max_set_cbs, (int32_t)(cb1 - cb0));
   }
   RNG(!h->accel_units || P.max_segs <= paam::kMaxUnitSegs,
       "a set has %d segments; with accelerator units at most %d", P.max_segs, paam::kMaxUnitSegs);
@@ -650,6 +651,7 @@ paam_status paam_chainset_upload(const paam_chainset_host *h, void *d_arena, siz
   cs->n_accel = P.n_accel;
   cs->max_tot = P.max_tot;
   cs->max_cb_segs = P.max_cb_segs;
+  cs->max_set_cbs = P.max_set_cbs;
   cs->max_buckets = P.max_buckets;
   cs->n_classes = (int)P.classes.size();
   for (int k = 0; k < cs->n_classes; ++k) cs->cls[k] = P.classes[k];
@@ -689,9 +691,15 @@ paam_status paam_des_batch(const paam_chainset *cs, const paam_des_opts *o,
                 "simulation holds at most %d chains, %d executors, %d segments per callback and "
                 "%d buckets per accelerator per set",
                 paam::kDesChains, paam::kDesExec, paam::kDesSegs, paam::kDesLevels);
+  if (paam::des_lds_bytes(cs->max_set_cbs, b.max_segs) > paam::kDesLdsMax)
+    return fail(PAAM_E_RANGE,
+                "simulation keeps a set's callbacks and segments in LDS: 12 bytes per callback plus "
+                "9 per segment, at most %zu bytes", paam::kDesLdsMax);
   if (b.n_sets == 0) return PAAM_OK;
   if (!d_offsets || !d_obs || !d_status) return fail(PAAM_E_INVAL, "null device buffer");
   paam::DesLaunch L;
+  L.max_cbs = std::max(cs->max_set_cbs, 1);
+  L.max_segs = std::max(b.max_segs, 1);
   L.b = b;
   L.o = *o;
   L.offsets = d_offsets;

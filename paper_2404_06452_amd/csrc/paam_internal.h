@@ -97,6 +97,7 @@ struct paam_chainset {
   int64_t n_exec, n_accel;
   int64_t max_tot;  // largest total demand of a set: sum of E, A + 2 kappa and epsilon
   int32_t max_cb_segs, max_buckets;  // largest eta of a callback, most buckets of an accelerator
+  int32_t max_set_cbs;               // most callbacks in a set
   int n_classes;
   paam::SizeClass cls[paam::kMaxClasses];
 };
@@ -208,8 +209,11 @@ struct DesLaunch {
   int64_t *obs;
   int8_t *status;
   int grid;
+  int32_t max_cbs, max_segs;  // per set, over the batch (sizes of the LDS tables)
 };
 int launch_des(const DesLaunch &L, void *stream);
+size_t des_lds_bytes(int64_t max_cbs, int64_t max_segs);
+constexpr size_t kDesLdsMax = 48 * 1024;  // LDS tables of one set
 
 size_t feat_wave_bytes(const DevBatch &b);
 // Feature tables of up to this size per wave live in LDS (else in the wave's
