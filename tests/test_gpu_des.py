@@ -105,6 +105,12 @@ def test_des_rejects_sets_beyond_its_limits():
     with pytest.raises(_paam.PaamError):
         _paam.simulate(dev, np.zeros(cs.n_chains, np.int64), 1, 1 << 41)
     dev.free()
+    # 8 chains of 600 callbacks: the set's tables exceed the 48 KB staged in LDS
+    cs = chaingen.generate(chaingen.PRESETS["small"].replace(cbs=(600, 600)), 1)
+    dev = _paam.Chainset(cs, device="cuda:0")
+    with pytest.raises(_paam.PaamError):
+        _paam.simulate(dev, np.zeros(cs.n_chains, np.int64), 1, 1000)
+    dev.free()
 
 
 @pytest.mark.gpu
