@@ -436,9 +436,33 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
   }
   __syncthreads();
 
-  // ---- Theorem 1 / Eq. (6): all sub-chains of the set together ----
+  // ---- verdict mode: the first iterate of every sub-chain (each interferer
+  //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
+  //      a chain whose sum of them passes its deadline proves the miss ----
   bool missed = false;
-  for (int sweep = 0;; ++sweep) {
+  if (!full) {
+    for (int s = lane; s < nrun; s += kWave) {
+      const int w = S.info[s];
+      const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
+      const double *wp = L.WP + e * C, *pt = L.Pt + e * C;
+      double lb = S.cst[s];
+      for (int h = 0; h < rho; ++h) lb += wp[h];
+      if (w & kHasP)
+        for (int h = rho + 1; h < C; ++h) lb += pt[h];
+      atomicAdd(&L.partial[rho], lb);
+    }
+    __syncthreads();
+    bool miss = false;
+    for (int rho = lane; rho < C; rho += kWave) {
+      if (L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho]) miss = true;
+      L.partial[rho] = 0.0;
+    }
+    missed = wave_any(miss);
+    __syncthreads();
+  }
+
+  // ---- Theorem 1 / Eq. (6): all sub-chains of the set together ----
+  for (int sweep = 0; !missed; ++sweep) {
     if (sweep >= kMaxIter) {
       if (lane == 0) L.misc[0] = 1;
       break;
