@@ -1285,12 +1285,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 // Backward over a chunk of kBwdChunk candidates per workgroup of 256 threads
 // (thread j = hidden unit j); writes this chunk's partial gradient.
 constexpr int kBwdChunk = 16;
+constexpr int kBwdRows = 64;  // feature rows staged in LDS at a time
+constexpr int kBwdThreads = NH;
 
-__global__ __launch_bounds__(256) void backward_kernel(BwdLaunch L) {
-  __shared__ float dz2[kBwdChunk][NH];
+__global__ __launch_bounds__(kBwdThreads) void backward_kernel(BwdLaunch L) {
+  __shared__ __attribute__((aligned(16))) float dz2[NH][kBwdChunk];  // [hidden unit][candidate]
   __shared__ float pq[kBwdChunk][NH];
   __shared__ float dp[kBwdChunk][NH];
-  __shared__ float xs[NF];
+  __shared__ __attribute__((aligned(16))) float xs[kBwdRows][NF];
   const int j = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * kBwdChunk;
   const int nc = (int)((L.n - c0) < kBwdChunk ? (L.n - c0) : kBwdChunk);
@@ -1306,7 +1308,7 @@ __global__ __launch_bounds__(256) void backward_kernel(BwdLaunch L) {
     const float dy = 2.0f * d * inv_n;
     const float h2 = bf16_value(a[256 + j]);
     const float g = h2 > 0.0f ? dy * w3j : 0.0f;
-    dz2[m][j] = g;
+    dz2[j][m] = g;
     pq[m][j] = bf16_value(a[j]);
     gw3 += dy * h2;
     gb2 += g;
@@ -1315,46 +1317,75 @@ __global__ __launch_bounds__(256) void backward_kernel(BwdLaunch L) {
       lsum += d * d;
     }
   }
+  for (int m = nc; m < kBwdChunk; ++m) dz2[j][m] = 0.0f;
   __syncthreads();
-  // dW2[i][j] = sum_m dz2[m][i] * pq[m][j]: thread j owns column j, so the
+  // dW2[i][j] = sum_m dz2(m, i) * pq[m][j]: thread j owns column j, so the
   // stores of every row are coalesced across the threads
   {
     float pqj[kBwdChunk];
     for (int m = 0; m < kBwdChunk; ++m) pqj[m] = m < nc ? pq[m][j] : 0.0f;
     for (int i = 0; i < NH; ++i) {
       float s = 0.0f;
-      for (int m = 0; m < nc; ++m) s += dz2[m][i] * pqj[m];
+      for (int m = 0; m < nc; ++m) s += dz2[i][m] * pqj[m];
       part[OW2 + i * NH + j] = s;
     }
   }
-  // dp[m][k = j] = sum_i dz2[m][i] * W2[i][j]
-  for (int m = 0; m < nc; ++m) {
-    float s = 0.0f;
-    for (int i = 0; i < NH; ++i) s += dz2[m][i] * bf16_value(W2[(size_t)i * NH + j]);
-    dp[m][j] = s;
+  // dp[m][k = j] = sum_i dz2(m, i) * W2[i][j]: each W2 element is read once
+  // and feeds the chunk's candidates (every sum still runs over i in order)
+  {
+    float acc[kBwdChunk];
+    for (int m = 0; m < kBwdChunk; ++m) acc[m] = 0.0f;
+    for (int i = 0; i < NH; ++i) {
+      const float w = bf16_value(W2[(size_t)i * NH + j]);
+      for (int m = 0; m < kBwdChunk; ++m) acc[m] += dz2[i][m] * w;
+    }
+    for (int m = 0; m < nc; ++m) dp[m][j] = acc[m];
   }
   __syncthreads();
-  // layer 1: recompute z1 per row, dz1 = dp / rows where z1 > 0
+  // layer 1: recompute z1 per row, dz1 = dp / rows where z1 > 0.  A
+  // candidate's rows are staged in LDS kBwdRows at a time; four rows are
+  // evaluated together (independent dot products), and their contributions
+  // are added in row order; a row whose z1 is not positive adds zeros, which
+  // leaves every sum's bits unchanged, so no lane branches.
   float gw1[NF];
   for (int f = 0; f < NF; ++f) gw1[f] = 0.0f;
   float gb1 = 0.0f;
   float w1[NF];
   for (int f = 0; f < NF; ++f) w1[f] = bf16_value(W1[(size_t)j * KP + f]);
   const float b1j = L.params[OB1 + j];
+  auto add_row = [&](const float *x, float g) {
+    gb1 += g;
+    for (int f = 0; f < NF; ++f) gw1[f] += g * x[f];
+  };
   for (int m = 0; m < nc; ++m) {
     const int64_t cand = c0 + m;
     const int rows = L.count[cand] > 0 ? L.count[cand] : 0;
     const float g = rows > 0 ? dp[m][j] / (float)rows : 0.0f;
     const uint16_t *X = L.feat + (size_t)cand * L.row_stride * NF;
-    for (int r = 0; r < rows; ++r) {
+    for (int r0 = 0; r0 < rows; r0 += kBwdRows) {
+      const int nr = rows - r0 < kBwdRows ? rows - r0 : kBwdRows;
+      __syncthreads();  // the previous tile is consumed
+      for (int i = j; i < nr * NF; i += kBwdThreads)
+        xs[i / NF][i % NF] = bf16_value(X[(size_t)r0 * NF + i]);
       __syncthreads();
-      if (j < NF) xs[j] = bf16_value(X[(size_t)r * NF + j]);
-      __syncthreads();
-      float z = b1j;
-      for (int f = 0; f < NF; ++f) z += w1[f] * xs[f];
-      if (z > 0.0f) {
-        gb1 += g;
-        for (int f = 0; f < NF; ++f) gw1[f] += g * xs[f];
+      int r = 0;
+      for (; r + 4 <= nr; r += 4) {
+        float z0 = b1j, z1 = b1j, z2 = b1j, z3 = b1j;
+        for (int f = 0; f < NF; ++f) {
+          z0 += w1[f] * xs[r][f];
+          z1 += w1[f] * xs[r + 1][f];
+          z2 += w1[f] * xs[r + 2][f];
+          z3 += w1[f] * xs[r + 3][f];
+        }
+        add_row(xs[r], z0 > 0.0f ? g : 0.0f);
+        add_row(xs[r + 1], z1 > 0.0f ? g : 0.0f);
+        add_row(xs[r + 2], z2 > 0.0f ? g : 0.0f);
+        add_row(xs[r + 3], z3 > 0.0f ? g : 0.0f);
+      }
+      for (; r < nr; ++r) {
+        float z = b1j;
+        for (int f = 0; f < NF; ++f) z += w1[f] * xs[r][f];
+        add_row(xs[r], z > 0.0f ? g : 0.0f);
       }
     }
   }
@@ -1451,7 +1482,7 @@ int launch_backward(const BwdLaunch &L, float *grad, float *loss, void *stream) 
   hipStream_t st = (hipStream_t)stream;
   if (L.n == 0) return 0;
   const int64_t chunks = backward_chunks(L.n);
-  hipLaunchKernelGGL(backward_kernel, dim3((unsigned)chunks), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(backward_kernel, dim3((unsigned)chunks), dim3(kBwdThreads), 0, st, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL(reduce_kernel, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, st,
