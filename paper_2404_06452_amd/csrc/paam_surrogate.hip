@@ -156,8 +156,6 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
   const int NA = (int)(b.set_accel_off[set + 1] - a0);
   const int NAm = NA > 0 ? NA : 1;
   const int64_t cb0 = b.set_cb_off[set];
-  const int64_t run0 = b.set_run_off[set];
-  const int nrun = (int)(b.set_run_off[set + 1] - run0);
   for (int e = threadIdx.x; e < X; e += kWave) t.hpx[e] = (int32_t)b.hpx_mask[x0 + e];
   for (int c = threadIdx.x; c < C; c += kWave) {
     int64_t E = 0, Ac = 0, ep = 0, Emax = 0;
@@ -173,15 +171,25 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
       t.Ahat[i] = t.Amax[i] = 0;
       t.dca[i] = t.nra[i] = 0;
     }
-    for (int s = 0; s < nrun; ++s) {
-      if (b.run_chain[run0 + s] != c) continue;
-      const int e = b.run_exec[run0 + s];
+    // the chain's callbacks in order; a sub-chain is a maximal run of
+    // consecutive callbacks on one executor (every table entry is a sum, a
+    // maximum or a union, so the order of the sub-chains does not matter)
+    const int jlo = b.chain_cb_lo[c0 + c];
+    const int jhi = c + 1 < C ? b.chain_cb_lo[c0 + c + 1] : (int)(b.set_cb_off[set + 1] - cb0);
+    int prev_e = -1;
+    uint32_t accs = 0;
+    for (int j = jlo; j < jhi; ++j) {
+      const int e = b.cb_exec[cb0 + j];
       const int ie = c * X + e;
-      ++S;
-      t.runs[ie] += 1;
-      mine |= 1u << e;
-      uint32_t accs = 0;
-      for (int j = b.run_cb_lo[run0 + s]; j < b.run_cb_hi[run0 + s]; ++j) {
+      if (e != prev_e) {
+        for (uint32_t m = accs; m; m &= m - 1) t.nra[c * NAm + (__ffs(m) - 1)] += 1;
+        accs = 0;
+        ++S;
+        t.runs[ie] += 1;
+        mine |= 1u << e;
+        prev_e = e;
+      }
+      {
         const int64_t Ej = scale_E(b.E[cb0 + j], u);
         ++ncb;
         E += Ej;
@@ -208,8 +216,8 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
         }
         t.bS[ie] = bj > t.bS[ie] ? bj : t.bS[ie];
       }
-      for (uint32_t m = accs; m; m &= m - 1) t.nra[c * NAm + (__ffs(m) - 1)] += 1;
     }
+    for (uint32_t m = accs; m; m &= m - 1) t.nra[c * NAm + (__ffs(m) - 1)] += 1;
     const int64_t T = b.T[c0 + c];
     int64_t qs = 0, qas = 0;
     for (int e = 0; e < X; ++e) {
@@ -937,9 +945,6 @@ __device__ __forceinline__ void features_body(FeatLaunch L) {
     }
     const int64_t c0 = L.b.set_chain_off[set];
     const int C = (int)(L.b.set_chain_off[set + 1] - c0);
-    const int64_t a0 = L.b.set_accel_off[set];
-    const int NA = (int)(L.b.set_accel_off[set + 1] - a0);
-    const int NAm = NA > 0 ? NA : 1;
     feat_build(L.b, set, u, t);
     if (t.setv[5] >= ((int64_t)1 << 40)) {
       // integer numerators could overflow: no features for this set
