@@ -145,6 +145,19 @@ __device__ __forceinline__ int64_t hpp_q(const FeatTables &t, int h, int e, int 
   return t.q[i] + (t.spin[h] ? t.qa[i] : 0);
 }
 
+// Wave-wide total and minimum of int64 values (butterfly over the 64 lanes).
+__device__ __forceinline__ int64_t wave_total_i64(int64_t v) {
+  for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t n = __shfl_xor(v, o);
+    v = n < v ? n : v;
+  }
+  return v;
+}
+
 // Order-independent tables of a set at utilisation scale u.  Lane c owns the
 // rows of chain c.  Ends synchronised.
 __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables &t) {
@@ -244,36 +257,46 @@ __device__ void feat_build(const DevBatch &b, int64_t set, int32_t u, FeatTables
     t.spin[c] = b.spin[c0 + c];
   }
   __syncthreads();
-  // column totals of the hpp weights per executor
-  for (int e = threadIdx.x; e < X; e += kWave) {
-    int64_t w = 0, q = 0;
-    for (int h = 0; h < C; ++h) {
-      w += hpp_w(t, h, e, X);
-      q += hpp_q(t, h, e, X);
-    }
-    t.colw[e] = w;
-    t.colw[X + e] = q;
-  }
-  if (threadIdx.x == 0) {
+  // column totals of the hpp weights per executor and the set-level sums:
+  // lanes over chains, then wave totals (integer sums, so exact in any order)
+  {
     int64_t sum_q = 0, sum_qA = 0, sum_dem = 0, Tmin = INT64_MAX, max_qe = 0, tot = 0;
-    for (int h = 0; h < C; ++h) {
+    for (int h = threadIdx.x; h < C; h += kWave) {
       tot += t.Ec[h] + t.Acc[h] + t.epc[h];
       sum_q += t.qsum[h];
       for (int a = 0; a < NA; ++a) sum_qA += t.qA[h * NAm + a];
       sum_dem += t.Ec[h] + t.Acc[h];
       Tmin = t.T[h] < Tmin ? t.T[h] : Tmin;
     }
+    tot = wave_total_i64(tot);
+    sum_q = wave_total_i64(sum_q);
+    sum_qA = wave_total_i64(sum_qA);
+    sum_dem = wave_total_i64(sum_dem);
+    Tmin = wave_min_i64(Tmin);
     for (int e = 0; e < X; ++e) {
-      int64_t s = 0;
-      for (int h = 0; h < C; ++h) s += t.q[h * X + e];
-      max_qe = s > max_qe ? s : max_qe;
+      int64_t w = 0, q = 0, qe = 0;
+      for (int h = threadIdx.x; h < C; h += kWave) {
+        w += hpp_w(t, h, e, X);
+        q += hpp_q(t, h, e, X);
+        qe += t.q[h * X + e];
+      }
+      w = wave_total_i64(w);
+      q = wave_total_i64(q);
+      qe = wave_total_i64(qe);
+      max_qe = qe > max_qe ? qe : max_qe;
+      if (threadIdx.x == 0) {
+        t.colw[e] = w;
+        t.colw[X + e] = q;
+      }
     }
-    t.setv[0] = sum_q;
-    t.setv[1] = sum_qA;
-    t.setv[2] = sum_dem;
-    t.setv[3] = Tmin;
-    t.setv[4] = max_qe;
-    t.setv[5] = tot;
+    if (threadIdx.x == 0) {
+      t.setv[0] = sum_q;
+      t.setv[1] = sum_qA;
+      t.setv[2] = sum_dem;
+      t.setv[3] = Tmin;
+      t.setv[4] = max_qe;
+      t.setv[5] = tot;
+    }
   }
   __syncthreads();
   // OS preemption by higher process-priority executors of the same core does
