@@ -438,9 +438,12 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
 
   // ---- verdict mode: the first iterate of every sub-chain (each interferer
   //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
-  //      a chain whose sum of them passes its deadline proves the miss ----
+  //      a chain whose sum of them passes its deadline proves the miss.
+  //      Each sub-chain's sum runs over the ranks, so the check costs about
+  //      as much as a sweep: it pays for sets of up to 64 chains, while for
+  //      larger ones the partial sums of the first sweep find a miss as early ----
   bool missed = false;
-  if (!full) {
+  if (!full && C <= kWave) {
     for (int s = lane; s < nrun; s += kWave) {
       const int w = S.info[s];
       const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
