@@ -45,7 +45,7 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "79413edf61082992b098755d256b5db77433e05e747915548104a24b27f1374c",
+TRAFFIC = {"sha256": "d748e5b59ae51744220458e5189e151a4d053c8e8b1f2ae0de55b1d8c822620a",
            "bytes_per_launch": 16.05e9, "sets": 1_000_000, "waves_per_cu": 20}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 

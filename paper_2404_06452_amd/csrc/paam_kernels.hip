@@ -731,20 +731,39 @@ __device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t 
       chain_R[c0 + c] = isinf(R) ? PAAM_INF : (int64_t)R;
     }
   }
-  if (lane == 0) {
-    int32_t w = -1;
-    int64_t wR = PAAM_INF;
-    if (!missed && (ok || full)) {
-      for (int c = 0; c < C; ++c) {
-        if (w < 0) {
-          w = c;
-          continue;
-        }
-        if (ratio_gt(L.partial[L.rank[c]], b.D[c0 + c], L.partial[L.rank[w]], b.D[c0 + w])) w = c;
+  // worst chain: the largest R/D (exact cross-multiplication), ties to the
+  // lowest chain index; each lane scans its chains, then a wave reduction
+  int32_t w = -1;
+  double wRd = 0.0;
+  int64_t wD = 1;
+  if (!missed && (ok || full)) {
+    for (int c = lane; c < C; c += kWave) {
+      const double R = L.partial[L.rank[c]];
+      const int64_t D = b.D[c0 + c];
+      if (w < 0 || ratio_gt(R, D, wRd, wD)) {
+        w = c;
+        wRd = R;
+        wD = D;
       }
-      const double R = L.partial[L.rank[w]];
-      wR = isinf(R) ? PAAM_INF : (int64_t)R;
     }
+    for (int off = 32; off > 0; off >>= 1) {
+      const int w2 = __shfl_xor(w, off);
+      const double R2 = __shfl_xor(wRd, off);
+      const int64_t D2 = __shfl_xor(wD, off);
+      bool take = false;
+      if (w2 >= 0) {
+        if (w < 0 || ratio_gt(R2, D2, wRd, wD)) take = true;
+        else if (!ratio_gt(wRd, wD, R2, D2) && w2 < w) take = true;
+      }
+      if (take) {
+        w = w2;
+        wRd = R2;
+        wD = D2;
+      }
+    }
+  }
+  if (lane == 0) {
+    const int64_t wR = (w < 0 || isinf(wRd)) ? PAAM_INF : (int64_t)wRd;
     set_sched[set] = L.misc[0] ? -1 : (ok ? 1 : 0);
     set_worst[set] = w;
     set_worst_R[set] = wR;
