@@ -183,12 +183,16 @@ constexpr int kConv = 1 << 27;    // last evaluation changed nothing
 constexpr int kInf = 1 << 28;     // the bound is past the cap
 
 // Analyses one set under the uploaded priorities and writes its outputs.
-// Called by all 64 lanes of a wave.
+// Called by all 64 lanes of a wave.  Always inlined: the LDS tables reach it
+// through plain pointers, and only inlined does the compiler see that they
+// address LDS and emit LDS atomics (an outlined copy would apply flat
+// atomics to them, which LDS does not take for fp64).
 // kSbLds: the blocking table is in LDS (else in the wave's global scratch).
 template <bool kSbLds>
-__device__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o, int64_t set, Lds &L,
-                            Scratch &S, int8_t *set_sched, int32_t *set_worst,
-                            int64_t *set_worst_R, int64_t *chain_R) {
+__device__ __forceinline__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o,
+                                            int64_t set, Lds &L, Scratch &S, int8_t *set_sched,
+                                            int32_t *set_worst, int64_t *set_worst_R,
+                                            int64_t *chain_R) {
   const int lane = threadIdx.x;
   const int64_t c0 = b.set_chain_off[set];
   const int C = (int)(b.set_chain_off[set + 1] - c0);
@@ -856,9 +860,10 @@ __device__ __forceinline__ double pack2(int hi, int lo) { return __hiloint2doubl
 // iterate stays below the least fixed point (the system is monotone and
 // starts at 0), so the final values are the least fixed points.
 template <class KR, bool kSbLds>
-__device__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o, int64_t set, KR kr,
-                              Lds &L, Scratch &S, int8_t *set_sched, int32_t *set_worst,
-                              int64_t *set_worst_R, int64_t *chain_R, int micro) {
+__device__ __forceinline__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o,
+                                              int64_t set, KR kr, Lds &L, Scratch &S,
+                                              int8_t *set_sched, int32_t *set_worst,
+                                              int64_t *set_worst_R, int64_t *chain_R, int micro) {
   const int lane = threadIdx.x;
   const int64_t c0 = b.set_chain_off[set];
   const int C = (int)(b.set_chain_off[set + 1] - c0);
