@@ -1153,6 +1153,7 @@ paam_status paam_features(const paam_chainset *cs, uint64_t seed, const int64_t 
   L.n_items = n_pairs;
   L.set0 = 0;
   L.n_cand = 0;
+  L.item = 1;
   L.util = 1000;
   L.row_stride = row_stride;
   L.feat = feat;
@@ -1248,7 +1249,8 @@ paam_status paam_score_bytes(const paam_chainset *cs, const paam_search_opts *o,
   if (st != PAAM_OK) return st;
   const int64_t S = score_chunk_sets(cs, o);
   const int64_t pairs = S * o->n_cand;
-  const int64_t items = S * ((o->n_cand + 63) / 64);
+  const int item = paam::feat_item(cs->dev);
+  const int64_t items = S * ((o->n_cand + item - 1) / item);
   const size_t feat = ((size_t)pairs * std::max(cs->dev.max_C, 1) * 48 * 2 + 255) & ~(size_t)255;
   const size_t cnt = ((size_t)pairs * 4 + 255) & ~(size_t)255;
   *ws_bytes = 256 + feat + cnt + (size_t)feat_grid(cs, items) * paam::feat_wave_bytes(cs->dev);
@@ -1270,7 +1272,8 @@ paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opt
     return fail(PAAM_E_RANGE, "a set's total demand reaches 2^40 ns");
   const int32_t Cm = std::max(cs->dev.max_C, 1);
   const int64_t S = score_chunk_sets(cs, o);
-  const int64_t per = (o->n_cand + 63) / 64;
+  const int item = paam::feat_item(cs->dev);
+  const int64_t per = (o->n_cand + item - 1) / item;
   unsigned char *w = static_cast<unsigned char *>(d_ws);
   const size_t feat_b = ((size_t)S * o->n_cand * Cm * 48 * 2 + 255) & ~(size_t)255;
   const size_t cnt_b = ((size_t)S * o->n_cand * 4 + 255) & ~(size_t)255;
@@ -1286,6 +1289,7 @@ paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opt
     F.n_items = ns * per;
     F.set0 = s0;
     F.n_cand = o->n_cand;
+    F.item = item;
     F.util = o->wcrt.util_permille;
     F.row_stride = Cm;
     F.feat = feat;

@@ -160,6 +160,7 @@ struct FeatLaunch {
   int64_t n_items;
   int64_t set0;
   int32_t n_cand, util, row_stride;
+  int32_t item;                 // consecutive candidates of a set per work item (range mode)
   uint16_t *feat;
   int32_t *count;
   unsigned long long *counter;
@@ -220,6 +221,10 @@ size_t feat_wave_bytes(const DevBatch &b);
 // global scratch); the host sizes the grid for the LDS it takes.
 constexpr size_t kFeatLdsMax = 40 * 1024;
 bool feat_in_lds(const DevBatch &b);
+// Candidates per work item of the scoring features: the LDS-table schedule
+// builds a set's tables once per item, so longer items pay there; the
+// prefix-scan schedule (global tables) is faster with shorter ones.
+int feat_item(const DevBatch &b);
 size_t backward_partial_stride();
 int64_t backward_chunks(int64_t n);
 int launch_features(const FeatLaunch &L, void *stream);

@@ -25,6 +25,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // sets: one candidate at a time over 64-rank chunks with running totals.
 constexpr int kMaxGroup = 16;
 constexpr int kScanC = 64;  // sets with more chains use the prefix-scan schedule
+// candidates per scoring work item: LDS-table schedule, prefix-scan schedule
+constexpr int kFeatItemLds = 128, kFeatItemScan = 64;
 constexpr int kFwd = 9;     // numerators of a chain from the prefix-scan schedule's forward pass
 // wave-uniform running totals of the prefix-scan schedule, in LDS: forward
 // (4 per executor, 4 per accelerator) and backward (3 and 3)
@@ -959,10 +961,10 @@ __device__ __forceinline__ void features_body(FeatLaunch L) {
       }
       u = (int32_t)uu;
     } else {
-      const int64_t per = (L.n_cand + 63) / 64;
+      const int64_t per = (L.n_cand + L.item - 1) / L.item;
       set = L.set0 + (int64_t)i / per;
-      k0 = ((int64_t)i % per) * 64;
-      n_k = L.n_cand - k0 < 64 ? L.n_cand - k0 : 64;
+      k0 = ((int64_t)i % per) * L.item;
+      n_k = L.n_cand - k0 < L.item ? L.n_cand - k0 : L.item;
       out0 = (set - L.set0) * L.n_cand + k0;
       u = L.util;
     }
@@ -1476,6 +1478,8 @@ size_t feat_wave_bytes(const DevBatch &b) {
 bool feat_in_lds(const DevBatch &b) {
   return b.max_C <= kScanC && feat_wave_bytes(b) <= kFeatLdsMax;
 }
+
+int feat_item(const DevBatch &b) { return feat_in_lds(b) ? kFeatItemLds : kFeatItemScan; }
 
 int launch_features(const FeatLaunch &L, void *stream) {
   hipStream_t st = (hipStream_t)stream;
