@@ -1257,28 +1257,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         }
       }
     }
+    // ---- layer 2 (64 x 256 x 256) and layer 3 partial sums.  Step k8 takes
+    // k = 32 k8 .. 32 k8 + 31 for the wave's four column tiles: the four
+    // pooled fragments (LDS) feed 16 MFMAs, and the W2 fragments (from L2) are
+    // loaded two steps ahead, the first two before the barrier, so no MFMA
+    // waits on a load issued just before it.  Every accumulator still sums k
+    // in increasing order.
+    auto load_w2 = [&](int k8, bf16x8 (&dst)[4]) {
+      for (int q = 0; q < 4; ++q) {
+        const int n = (w * 4 + q) * 16 + li;
+        dst[q] = load8(W2 + (size_t)n * NH + 32 * k8 + 8 * lg);
+      }
+    };
+    bf16x8 wb[3][4];
+    load_w2(0, wb[0]);
+    load_w2(1, wb[1]);
     __syncthreads();
-    // ---- layer 2 (64 x 256 x 256) and layer 3 partial sums
+    f32x4 acc2[4][4];
+    for (int q = 0; q < 4; ++q)
+      for (int mt = 0; mt < 4; ++mt) acc2[q][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k8 = 0; k8 < NH / 32; ++k8) {
+      if (k8 + 2 < NH / 32) load_w2(k8 + 2, wb[(k8 + 2) % 3]);
+      bf16x8 a[4];
+      for (int mt = 0; mt < 4; ++mt) a[mt] = load8(Pq + (mt * 16 + li) * kPqStride + 32 * k8 + 8 * lg);
+      for (int q = 0; q < 4; ++q)
+        for (int mt = 0; mt < 4; ++mt)
+          acc2[q][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], wb[k8 % 3][q], acc2[q][mt], 0, 0, 0);
+    }
     float yp[4][4];
     for (int mt = 0; mt < 4; ++mt)
       for (int j = 0; j < 4; ++j) yp[mt][j] = 0.0f;
     for (int q = 0; q < 4; ++q) {
       const int n = (w * 4 + q) * 16 + li;
-      f32x4 acc[4];
-      for (int mt = 0; mt < 4; ++mt) acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      for (int kk = 0; kk < NH; kk += 32) {
-        const bf16x8 bb = load8(W2 + (size_t)n * NH + kk + 8 * lg);
-        for (int mt = 0; mt < 4; ++mt) {
-          const bf16x8 a = load8(Pq + (mt * 16 + li) * kPqStride + kk + 8 * lg);
-          acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[mt], 0, 0, 0);
-        }
-      }
       const float bias = b2[n];
       const float wv = bf16_value(w3[n]);
       for (int mt = 0; mt < 4; ++mt) {
         for (int j = 0; j < 4; ++j) {
           const int mb = mt * 16 + 4 * lg + j;
-          const float z = acc[mt][j] + bias;
+          const float z = acc2[q][mt][j] + bias;
           const uint16_t hq = bf16_rne(z > 0.0f ? z : 0.0f);
           yp[mt][j] += wv * bf16_value(hq);
           if (L.act && base + mb < L.n)
