@@ -1154,6 +1154,9 @@ paam_status paam_features(const paam_chainset *cs, uint64_t seed, const int64_t 
   L.set0 = 0;
   L.n_cand = 0;
   L.item = 1;
+  L.set_tables = nullptr;
+  L.set_table_stride = 0;
+  L.n_table_sets = 0;
   L.util = 1000;
   L.row_stride = row_stride;
   L.feat = feat;
@@ -1253,7 +1256,10 @@ paam_status paam_score_bytes(const paam_chainset *cs, const paam_search_opts *o,
   const int64_t items = S * ((o->n_cand + item - 1) / item);
   const size_t feat = ((size_t)pairs * std::max(cs->dev.max_C, 1) * 48 * 2 + 255) & ~(size_t)255;
   const size_t cnt = ((size_t)pairs * 4 + 255) & ~(size_t)255;
-  *ws_bytes = 256 + feat + cnt + (size_t)feat_grid(cs, items) * paam::feat_wave_bytes(cs->dev);
+  // prefix-scan schedule: one shared copy of each chunk set's tables
+  const size_t tables = paam::feat_in_lds(cs->dev) ? 0 : (size_t)S * paam::feat_wave_bytes(cs->dev);
+  *ws_bytes = 256 + feat + cnt + (size_t)feat_grid(cs, items) * paam::feat_wave_bytes(cs->dev) +
+              tables;
   return PAAM_OK;
 }
 
@@ -1280,6 +1286,9 @@ paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opt
   uint16_t *feat = reinterpret_cast<uint16_t *>(w + 256);
   int32_t *count = reinterpret_cast<int32_t *>(w + 256 + feat_b);
   unsigned char *scr = w + 256 + feat_b + cnt_b;
+  const bool shared = !paam::feat_in_lds(cs->dev);
+  unsigned char *tables =
+      scr + (size_t)feat_grid(cs, S * per) * paam::feat_wave_bytes(cs->dev);
   for (int64_t s0 = 0; s0 < cs->dev.n_sets; s0 += S) {
     const int64_t ns = std::min<int64_t>(S, cs->dev.n_sets - s0);
     paam::FeatLaunch F;
@@ -1292,12 +1301,19 @@ paam_status paam_score_candidates(const paam_chainset *cs, const paam_search_opt
     F.item = item;
     F.util = o->wcrt.util_permille;
     F.row_stride = Cm;
+    F.set_tables = shared ? tables : nullptr;
+    F.set_table_stride = paam::feat_wave_bytes(cs->dev);
+    F.n_table_sets = shared ? ns : 0;
     F.feat = feat;
     F.count = count;
     F.counter = reinterpret_cast<unsigned long long *>(w);
     F.scratch = scr;
     F.scratch_stride = paam::feat_wave_bytes(cs->dev);
     F.grid = feat_grid(cs, F.n_items);
+    if (shared) {
+      int e = paam::launch_feat_tables(F, (int)std::min<int64_t>(ns, (int64_t)num_cus() * 8), stream);
+      if (e != 0) return hip_fail((hipError_t)e, "feature tables launch");
+    }
     int e = paam::launch_features(F, stream);
     if (e != 0) return hip_fail((hipError_t)e, "features launch");
     paam::FwdLaunch L{d_params, d_packed, feat, count, ns * o->n_cand, Cm,

@@ -161,6 +161,13 @@ struct FeatLaunch {
   int64_t set0;
   int32_t n_cand, util, row_stride;
   int32_t item;                 // consecutive candidates of a set per work item (range mode)
+  // range mode, prefix-scan schedule: the order-independent tables of set
+  // set0 + s at set_tables + s * set_table_stride, built by launch_feat_tables
+  // for n_table_sets sets and shared by the set's items (null: each item
+  // builds them in its wave's scratch)
+  unsigned char *set_tables;
+  size_t set_table_stride;
+  int64_t n_table_sets;
   uint16_t *feat;
   int32_t *count;
   unsigned long long *counter;
@@ -228,6 +235,7 @@ int feat_item(const DevBatch &b);
 size_t backward_partial_stride();
 int64_t backward_chunks(int64_t n);
 int launch_features(const FeatLaunch &L, void *stream);
+int launch_feat_tables(const FeatLaunch &L, int grid, void *stream);
 int launch_pack(const float *params, uint16_t *packed, void *stream);
 int launch_forward(const FwdLaunch &L, void *stream);
 int launch_backward(const BwdLaunch &L, float *grad, float *loss, void *stream);

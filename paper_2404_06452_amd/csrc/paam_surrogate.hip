@@ -26,7 +26,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxGroup = 16;
 constexpr int kScanC = 64;  // sets with more chains use the prefix-scan schedule
 // candidates per scoring work item: LDS-table schedule, prefix-scan schedule
-constexpr int kFeatItemLds = 128, kFeatItemScan = 64;
+constexpr int kFeatItemLds = 128, kFeatItemScan = 8;
 constexpr int kFwd = 9;     // numerators of a chain from the prefix-scan schedule's forward pass
 // wave-uniform running totals of the prefix-scan schedule, in LDS: forward
 // (4 per executor, 4 per accelerator) and backward (3 and 3)
@@ -941,11 +941,12 @@ __device__ __forceinline__ void features_body(FeatLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char *base = kLds ? lds_raw : L.scratch + (size_t)blockIdx.x * L.scratch_stride;
   const int NAmx = L.b.max_NA > 0 ? L.b.max_NA : 1;
-  FeatTables t = carve_feat(base, L.b.max_C, L.b.max_X, NAmx);
+  const FeatTables tw = carve_feat(base, L.b.max_C, L.b.max_X, NAmx);
   __shared__ int64_t scan_carry[kScanCarry];
   const int lane = threadIdx.x;
   // grid-stride: the item index is wave-uniform by construction
   for (int64_t i = blockIdx.x; i < L.n_items; i += gridDim.x) {
+    FeatTables t = tw;
     int64_t set, k0, n_k, out0;
     int32_t u;
     if (L.pairs) {
@@ -970,13 +971,30 @@ __device__ __forceinline__ void features_body(FeatLaunch L) {
     }
     const int64_t c0 = L.b.set_chain_off[set];
     const int C = (int)(L.b.set_chain_off[set + 1] - c0);
-    feat_build(L.b, set, u, t);
+    const bool shared = !kLds && !L.pairs && L.set_tables != nullptr;
+    if (shared) {
+      // the set's tables and row templates were built by feat_tables_kernel;
+      // the walk state, ranks, inversion counts and forward numerators stay
+      // in the wave's scratch
+      t = carve_feat(L.set_tables + (size_t)(set - L.set0) * L.set_table_stride, L.b.max_C,
+                     L.b.max_X, NAmx);
+      t.order = tw.order;
+      t.rank = tw.rank;
+      t.buf = tw.buf;
+      t.ordg = tw.ordg;
+      t.rankg = tw.rankg;
+      t.fwd = tw.fwd;
+      t.inv = tw.inv;
+    } else {
+      feat_build(L.b, set, u, t);
+    }
     if (t.setv[5] >= ((int64_t)1 << 40)) {
       // integer numerators could overflow: no features for this set
       for (int64_t k = lane; k < n_k; k += kWave) L.count[out0 + k] = -2;
       continue;
     }
-    for (int c = lane; c < C; c += kWave) feat_template(L.b, set, t, c);
+    if (!shared)
+      for (int c = lane; c < C; c += kWave) feat_template(L.b, set, t, c);
     for (int c = lane; c < C; c += kWave) {
       const int r = L.b.rank0[c0 + c];
       t.order[r] = c;
@@ -1037,6 +1055,24 @@ __device__ __forceinline__ void features_body(FeatLaunch L) {
       for (int g = lane; g < ng; g += kWave) L.count[out0 + (kb - k0) + g] = C;
       __syncthreads();
     }
+  }
+}
+
+// The order-independent tables and row templates of sets set0 .. set0 +
+// n_table_sets - 1, one wave per set, into the per-set buffers that the
+// candidate items of the prefix-scan schedule then share (read only).
+__global__ __launch_bounds__(kWave) void feat_tables_kernel(FeatLaunch L) {
+  const int NAmx = L.b.max_NA > 0 ? L.b.max_NA : 1;
+  for (int64_t s = blockIdx.x; s < L.n_table_sets; s += gridDim.x) {
+    const int64_t set = L.set0 + s;
+    FeatTables t =
+        carve_feat(L.set_tables + (size_t)s * L.set_table_stride, L.b.max_C, L.b.max_X, NAmx);
+    feat_build(L.b, set, L.util, t);
+    if (t.setv[5] < ((int64_t)1 << 40)) {
+      const int C = (int)(L.b.set_chain_off[set + 1] - L.b.set_chain_off[set]);
+      for (int c = threadIdx.x; c < C; c += kWave) feat_template(L.b, set, t, c);
+    }
+    __syncthreads();
   }
 }
 
@@ -1497,6 +1533,13 @@ bool feat_in_lds(const DevBatch &b) {
 }
 
 int feat_item(const DevBatch &b) { return feat_in_lds(b) ? kFeatItemLds : kFeatItemScan; }
+
+int launch_feat_tables(const FeatLaunch &L, int grid, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (L.n_table_sets == 0) return 0;
+  hipLaunchKernelGGL(feat_tables_kernel, dim3(grid), dim3(kWave), 0, st, L);
+  return (int)hipGetLastError();
+}
 
 int launch_features(const FeatLaunch &L, void *stream) {
   hipStream_t st = (hipStream_t)stream;

@@ -251,8 +251,9 @@ MID = dict(chains=(65, 140), n_accel=3, max_seg_per_cb=2, n_buckets=5, eps=391_0
 @pytest.mark.parametrize("preset,n_sets,n_cand", [("search", 12, 70), ("mid", 3, 150),
                                                    ("mixed", 4, 80)])
 def test_score_candidates_equals_explicit_path(preset, n_sets, n_cand):
-    # range mode walks each run of 64 candidates one swap at a time (updated
-    # inversion counts on sets of more than 64 chains); the explicit path
+    # range mode walks each run of consecutive candidates one swap at a time
+    # (updated inversion counts on sets of more than 64 chains, whose tables
+    # are built once per set and shared by its runs); the explicit path
     # computes every pair from scratch
     if preset == "mid":
         params = chaingen.PRESETS["large"].replace(**MID)
