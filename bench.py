@@ -45,7 +45,7 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "4dba4aa40badea0de6bdfbf76fdf8a3f72ce98f3acd9c7e45259d289ef98be9d",
+TRAFFIC = {"sha256": "63827a12ed32f09326a152176c84728e42c549d4b2a8be3c7b7c9b6367fa4ec8",
            "bytes_per_launch": 16.05e9, "sets": 1_000_000, "waves_per_cu": 20}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 

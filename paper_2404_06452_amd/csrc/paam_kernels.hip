@@ -188,11 +188,13 @@ constexpr int kInf = 1 << 28;     // the bound is past the cap
 // address LDS and emit LDS atomics (an outlined copy would apply flat
 // atomics to them, which LDS does not take for fp64).
 // kSbLds: the blocking table is in LDS (else in the wave's global scratch).
+// try_early: in verdict mode, run the miss check at the segments' lower
+// bounds before Lemma 2 (below); returns whether that check proved the miss.
 template <bool kSbLds>
-__device__ __forceinline__ void analyse_set(const DevBatch &b, const paam_wcrt_opts &o,
+__device__ __forceinline__ bool analyse_set(const DevBatch &b, const paam_wcrt_opts &o,
                                             int64_t set, Lds &L, Scratch &S, int8_t *set_sched,
                                             int32_t *set_worst, int64_t *set_worst_R,
-                                            int64_t *chain_R) {
+                                            int64_t *chain_R, bool try_early) {
   const int lane = threadIdx.x;
   const int64_t c0 = b.set_chain_off[set];
   const int C = (int)(b.set_chain_off[set + 1] - c0);
@@ -301,171 +303,198 @@ __device__ __forceinline__ void analyse_set(const DevBatch &b, const paam_wcrt_o
   }
   __syncthreads();
 
-  // ---- Lemma 2 / Eq. (3): per-segment handling time ----
-  for (int gb = 0; gb < nseg; gb += kWave) {
-    const int g = gb + lane;
-    const bool valid = g < nseg;
-    int rho = 0, a = 0;
-    double base = 0.0, capv = 0.0;
-    if (valid) {
-      a = b.seg_accel[g0 + g];
-      rho = L.rank[b.seg_chain[g0 + g]];
-      base = S.segAs[g] + L.Bacc[a * C + rho];
-      capv = L.Dd[rho] * capm;
-    }
-    const double *Ah = L.Ahat + a * C;
-    double h = 0.0;
-    bool done = !valid;
-    for (int it = 0; wave_any(!done); ++it) {
-      if (it >= kMaxIter) {
-        if (!done) L.misc[0] = 1;
-        break;
+  // Verdict mode, sets of up to 64 chains: a first pass with every segment's
+  // handling time at its lower bound A* + same-bucket blocking (the base of
+  // Lemma 2, below each of its iterates) runs the miss check below before
+  // Lemma 2.  Every quantity built from those times only grows with them, so
+  // the check stays a lower bound; a candidate whose miss it proves skips
+  // Lemma 2 and the rest.  Otherwise the tables are cleared and the second
+  // pass runs with the Lemma 2 times.
+  const bool early = !full && C <= kWave;
+  bool missed = false, early_miss = false;
+  for (int pass = early && try_early ? 0 : 1; pass < 2 && !missed; ++pass) {
+    if (pass == 0) {
+      for (int g = lane; g < nseg; g += kWave) {
+        const int a = b.seg_accel[g0 + g];
+        const int rho = L.rank[b.seg_chain[g0 + g]];
+        S.segH[g] = S.segAs[g] + L.Bacc[a * C + rho];
       }
-      if (!done) {
-        double n0 = base, n1 = 0.0;
-        int k = 0;
-        for (; k + 1 < rho; k += 2) {
-          const double2 q0 = L.KR[k], q1 = L.KR[k + 1];
-          n0 = fma(mu_term(h, q0.x, q0.y), Ah[k], n0);
-          n1 = fma(mu_term(h, q1.x, q1.y), Ah[k + 1], n1);
+      __syncthreads();
+    } else {
+      if (early && try_early) {
+        for (int i = lane; i < X * C; i += kWave) {
+          L.WP[i] = 0.0;
+          L.Pt[i] = 0.0;
+          SB[i] = 0.0;
         }
-        if (k < rho) {
-          const double2 q0 = L.KR[k];
-          n0 = fma(mu_term(h, q0.x, q0.y), Ah[k], n0);
+        __syncthreads();
+      }
+      // ---- Lemma 2 / Eq. (3): per-segment handling time ----
+      for (int gb = 0; gb < nseg; gb += kWave) {
+        const int g = gb + lane;
+        const bool valid = g < nseg;
+        int rho = 0, a = 0;
+        double base = 0.0, capv = 0.0;
+        if (valid) {
+          a = b.seg_accel[g0 + g];
+          rho = L.rank[b.seg_chain[g0 + g]];
+          base = S.segAs[g] + L.Bacc[a * C + rho];
+          capv = L.Dd[rho] * capm;
         }
-        const double nxt = n0 + n1;
-        if (nxt > capv) {
-          h = INFINITY;
-          done = true;
-        } else if (nxt == h) {
-          done = true;
-        } else {
-          h = nxt;
+        const double *Ah = L.Ahat + a * C;
+        double h = 0.0;
+        bool done = !valid;
+        for (int it = 0; wave_any(!done); ++it) {
+          if (it >= kMaxIter) {
+            if (!done) L.misc[0] = 1;
+            break;
+          }
+          if (!done) {
+            double n0 = base, n1 = 0.0;
+            int k = 0;
+            for (; k + 1 < rho; k += 2) {
+              const double2 q0 = L.KR[k], q1 = L.KR[k + 1];
+              n0 = fma(mu_term(h, q0.x, q0.y), Ah[k], n0);
+              n1 = fma(mu_term(h, q1.x, q1.y), Ah[k + 1], n1);
+            }
+            if (k < rho) {
+              const double2 q0 = L.KR[k];
+              n0 = fma(mu_term(h, q0.x, q0.y), Ah[k], n0);
+            }
+            const double nxt = n0 + n1;
+            if (nxt > capv) {
+              h = INFINITY;
+              done = true;
+            } else if (nxt == h) {
+              done = true;
+            } else {
+              h = nxt;
+            }
+          }
         }
+        if (valid) S.segH[g] = h;
+      }
+      __syncthreads();
+    }
+    // ---- sub-chains: own demand, Lemma 2 sum, Lemma 3 constant, overheads,
+    //      and each callback as a blocking candidate ----
+    const bool safe = o.blocking == PAAM_BLOCK_SAFE;
+    for (int s = lane; s < nrun; s += kWave) {
+      const int64_t rr = run0 + s;
+      const int c = b.run_chain[rr];
+      const int e = b.run_exec[rr];
+      const int rho = L.rank[c];
+      double E = 0.0, L2 = 0.0, A0 = 0.0, eps = 0.0, bmax = 0.0;
+      int delta = 0, accm = 0;
+      for (int j = b.run_cb_lo[rr]; j < b.run_cb_hi[rr]; ++j) {
+        const double Ej = scale_time(b.E[cb0 + j], u);
+        E += Ej;
+        double bj = Ej;
+        for (int64_t gg = b.cb_seg_off[cb0 + j]; gg < b.cb_seg_off[cb0 + j + 1]; ++gg) {
+          const int g = (int)(gg - g0);
+          const int a = b.seg_accel[gg];
+          const double Hg = S.segH[g];
+          const double ea = (double)b.aeps[a0 + a];
+          L2 += Hg;
+          A0 += S.segAs[g] + L.Bacc[a * C + rho];
+          eps += ea;
+          if (safe) bj += Hg + ea;
+          ++delta;
+          accm |= 1 << a;
+        }
+        bmax = fmax(bmax, bj);
+      }
+      atomic_max_nonneg(&SB[e * C + rho], bmax);
+      const bool needL3 =
+          delta > 0 && (o.bound == PAAM_BOUND_L3 || (o.bound == PAAM_BOUND_MIN && delta >= 2));
+      // H* of a sub-chain that does not need Lemma 3 during the iteration.  With
+      // one segment, Lemma 3 is the recurrence of Lemma 2 and R >= H at the
+      // fixed point, so H* = L2 + eps there; with no HP request of positive
+      // length, Lemma 3 is the constant A0 <= L2 (also at an unbounded window).
+      bool hp_acc = false;
+      for (int a = 0; a < NA; ++a)
+        if (((accm >> a) & 1) && L.misc[1 + a] < rho) hp_acc = true;
+      double hs0 = delta == 0 ? 0.0 : (hp_acc || o.bound == PAAM_BOUND_L2 ? L2 : A0) + eps;
+      if (needL3) hs0 = 0.0;  // a valid start below the fixed point
+      // per chain and executor: E + H* (own executor's weight) in WP, and
+      // E + spin() (H* if the chain busy-waits, else its epsilon sum) in Pt
+      atomicAdd(&L.WP[e * C + rho], E + hs0);
+      atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
+      S.r[s] = 0.0;
+      // constant part of the recurrence: E, blocking (added below) and, when H*
+      // does not follow Lemma 3 during the iteration, H* itself; only the
+      // others keep H* as state
+      S.hs[s] = hs0;
+      S.cst[s] = E + (needL3 ? 0.0 : hs0);
+      S.L2[s] = L2;
+      S.A0[s] = A0;
+      S.eps[s] = eps;
+      S.info[s] = rho | (e << kExecShift) | (accm << kAccShift) | (needL3 ? kNeedL3 : 0) |
+                  (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
+    }
+    __syncthreads();
+    // suffix maximum of blocking candidates per executor, lowest priority up
+    for (int e = lane; e < X; e += kWave) {
+      double m = 0.0;
+      for (int rho = C - 1; rho >= 0; --rho) {
+        m = fmax(m, SB[e * C + rho]);
+        SB[e * C + rho] = m;
       }
     }
-    if (valid) S.segH[g] = h;
-  }
-  __syncthreads();
-
-  // ---- sub-chains: own demand, Lemma 2 sum, Lemma 3 constant, overheads,
-  //      and each callback as a blocking candidate ----
-  const bool safe = o.blocking == PAAM_BLOCK_SAFE;
-  for (int s = lane; s < nrun; s += kWave) {
-    const int64_t rr = run0 + s;
-    const int c = b.run_chain[rr];
-    const int e = b.run_exec[rr];
-    const int rho = L.rank[c];
-    double E = 0.0, L2 = 0.0, A0 = 0.0, eps = 0.0, bmax = 0.0;
-    int delta = 0, accm = 0;
-    for (int j = b.run_cb_lo[rr]; j < b.run_cb_hi[rr]; ++j) {
-      const double Ej = scale_time(b.E[cb0 + j], u);
-      E += Ej;
-      double bj = Ej;
-      for (int64_t gg = b.cb_seg_off[cb0 + j]; gg < b.cb_seg_off[cb0 + j + 1]; ++gg) {
-        const int g = (int)(gg - g0);
-        const int a = b.seg_accel[gg];
-        const double Hg = S.segH[g];
-        const double ea = (double)b.aeps[a0 + a];
-        L2 += Hg;
-        A0 += S.segAs[g] + L.Bacc[a * C + rho];
-        eps += ea;
-        if (safe) bj += Hg + ea;
-        ++delta;
-        accm |= 1 << a;
-      }
-      bmax = fmax(bmax, bj);
-    }
-    atomic_max_nonneg(&SB[e * C + rho], bmax);
-    const bool needL3 =
-        delta > 0 && (o.bound == PAAM_BOUND_L3 || (o.bound == PAAM_BOUND_MIN && delta >= 2));
-    // H* of a sub-chain that does not need Lemma 3 during the iteration.  With
-    // one segment, Lemma 3 is the recurrence of Lemma 2 and R >= H at the
-    // fixed point, so H* = L2 + eps there; with no HP request of positive
-    // length, Lemma 3 is the constant A0 <= L2 (also at an unbounded window).
-    bool hp_acc = false;
-    for (int a = 0; a < NA; ++a)
-      if (((accm >> a) & 1) && L.misc[1 + a] < rho) hp_acc = true;
-    double hs0 = delta == 0 ? 0.0 : (hp_acc || o.bound == PAAM_BOUND_L2 ? L2 : A0) + eps;
-    if (needL3) hs0 = 0.0;  // a valid start below the fixed point
-    // per chain and executor: E + H* (own executor's weight) in WP, and
-    // E + spin() (H* if the chain busy-waits, else its epsilon sum) in Pt
-    atomicAdd(&L.WP[e * C + rho], E + hs0);
-    atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
-    S.r[s] = 0.0;
-    // constant part of the recurrence: E, blocking (added below) and, when H*
-    // does not follow Lemma 3 during the iteration, H* itself; only the
-    // others keep H* as state
-    S.hs[s] = hs0;
-    S.cst[s] = E + (needL3 ? 0.0 : hs0);
-    S.L2[s] = L2;
-    S.A0[s] = A0;
-    S.eps[s] = eps;
-    S.info[s] = rho | (e << kExecShift) | (accm << kAccShift) | (needL3 ? kNeedL3 : 0) |
-                (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
-  }
-  __syncthreads();
-  // suffix maximum of blocking candidates per executor, lowest priority up
-  for (int e = lane; e < X; e += kWave) {
-    double m = 0.0;
-    for (int rho = C - 1; rho >= 0; --rho) {
-      m = fmax(m, SB[e * C + rho]);
-      SB[e * C + rho] = m;
-    }
-  }
-  __syncthreads();
-  // blocking by one callback of a lower priority chain on the executor
-  for (int s = lane; s < nrun; s += kWave) {
-    const int w = S.info[s];
-    const int rho = w & kRankMask;
-    const int e = (w >> kExecShift) & 31;
-    S.cst[s] += rho + 1 < C ? SB[e * C + rho + 1] : 0.0;
-  }
-  __syncthreads();
-  // interference weights at the starting H*: WP[e][h] = E + H* of h on e (hp
-  // term of a lower-ranked chain) + hpp weight; Pt[e][h] = hpp weight alone,
-  // the sum over the core's higher-priority executors e2 of E + spin() of h
-  // on e2.  From here on every change of an H* is added to the weights it
-  // enters, and the ranks it touches are recorded for the next sweep.
-  for (int i = lane; i < X * C; i += kWave) {
-    const int e = i / C, h = i - e * C;
-    double p = 0.0;
-    for (uint32_t m = b.hpx_mask[x0 + e]; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
-    SB[i] = p;  // blocking candidates are dead
-  }
-  __syncthreads();
-  for (int i = lane; i < X * C; i += kWave) {
-    L.WP[i] += SB[i];
-    L.Pt[i] = SB[i];
-  }
-  __syncthreads();
-
-  // ---- verdict mode: the first iterate of every sub-chain (each interferer
-  //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
-  //      a chain whose sum of them passes its deadline proves the miss.
-  //      Each sub-chain's sum runs over the ranks, so the check costs about
-  //      as much as a sweep: it pays for sets of up to 64 chains, while for
-  //      larger ones the partial sums of the first sweep find a miss as early ----
-  bool missed = false;
-  if (!full && C <= kWave) {
+    __syncthreads();
+    // blocking by one callback of a lower priority chain on the executor
     for (int s = lane; s < nrun; s += kWave) {
       const int w = S.info[s];
-      const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
-      const double *wp = L.WP + e * C, *pt = L.Pt + e * C;
-      double lb = S.cst[s];
-      for (int h = 0; h < rho; ++h) lb += wp[h];
-      if (w & kHasP)
-        for (int h = rho + 1; h < C; ++h) lb += pt[h];
-      atomicAdd(&L.partial[rho], lb);
+      const int rho = w & kRankMask;
+      const int e = (w >> kExecShift) & 31;
+      S.cst[s] += rho + 1 < C ? SB[e * C + rho + 1] : 0.0;
     }
     __syncthreads();
-    bool miss = false;
-    for (int rho = lane; rho < C; rho += kWave) {
-      if (L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho]) miss = true;
-      L.partial[rho] = 0.0;
+    // interference weights at the starting H*: WP[e][h] = E + H* of h on e (hp
+    // term of a lower-ranked chain) + hpp weight; Pt[e][h] = hpp weight alone,
+    // the sum over the core's higher-priority executors e2 of E + spin() of h
+    // on e2.  From here on every change of an H* is added to the weights it
+    // enters, and the ranks it touches are recorded for the next sweep.
+    for (int i = lane; i < X * C; i += kWave) {
+      const int e = i / C, h = i - e * C;
+      double p = 0.0;
+      for (uint32_t m = b.hpx_mask[x0 + e]; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
+      SB[i] = p;  // blocking candidates are dead
     }
-    missed = wave_any(miss);
     __syncthreads();
+    for (int i = lane; i < X * C; i += kWave) {
+      L.WP[i] += SB[i];
+      L.Pt[i] = SB[i];
+    }
+    __syncthreads();
+
+    // ---- verdict mode: the first iterate of every sub-chain (each interferer
+    //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
+    //      a chain whose sum of them passes its deadline proves the miss.
+    //      Each sub-chain's sum runs over the ranks, so the check costs about
+    //      as much as a sweep: it pays for sets of up to 64 chains, while for
+    //      larger ones the partial sums of the first sweep find a miss as early ----
+    if (early) {
+      for (int s = lane; s < nrun; s += kWave) {
+        const int w = S.info[s];
+        const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
+        const double *wp = L.WP + e * C, *pt = L.Pt + e * C;
+        double lb = S.cst[s];
+        for (int h = 0; h < rho; ++h) lb += wp[h];
+        if (w & kHasP)
+          for (int h = rho + 1; h < C; ++h) lb += pt[h];
+        atomicAdd(&L.partial[rho], lb);
+      }
+      __syncthreads();
+      bool miss = false;
+      for (int rho = lane; rho < C; rho += kWave) {
+        if (L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho]) miss = true;
+        L.partial[rho] = 0.0;
+      }
+      missed = wave_any(miss);
+      early_miss = missed && pass == 0;
+      __syncthreads();
+    }
   }
 
   // ---- Theorem 1 / Eq. (6): all sub-chains of the set together ----
@@ -773,6 +802,7 @@ __device__ __forceinline__ void analyse_set(const DevBatch &b, const paam_wcrt_o
     set_worst_R[set] = wR;
   }
   __syncthreads();
+  return early_miss;
 }
 
 // ------------------------- queue-driven analysis ---------------------------
@@ -1672,6 +1702,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
     DevBatch bq = L.b;
     bq.rank0 = q.rank - c0;
     int found = -1, n_eval = 0;
+    // the miss check before Lemma 2 is tried until it first fails on the set
+    // (on sets whose candidates it does not reject, it is work on top)
+    bool early = true;
     int64_t cur = 0;  // candidate the slot's order holds
     if (L.o.guided) {
       const float *sc = L.o.d_scores + set * (int64_t)n_cand;
@@ -1716,7 +1749,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
         }
         walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
         cur = k;
-        analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+        if (!analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set,
+                                 nullptr, early))
+          early = false;
         ++n_eval;
         int v = 0;
         if (threadIdx.x == 0) v = q.sched[0];  // written by lane 0 of analyse_set
@@ -1737,7 +1772,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
           }
           walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
           cur = k;
-          analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+          if (!analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set,
+                                   q.worst_R - set, nullptr, early))
+            early = false;
           ++n_eval;
           int v = 0;
           if (threadIdx.x == 0) v = q.sched[0];
@@ -1752,7 +1789,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchLaunch L) {
       for (int k = 0; k < n_cand; ++k) {
         walk_order(q.order, q.rank, C, L.o.seed, set, cur, k, q.buf);
         cur = k;
-        analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+        if (!analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set,
+                                 nullptr, early))
+          early = false;
         ++n_eval;
         int v = 0;
         if (threadIdx.x == 0) v = q.sched[0];
@@ -1806,7 +1845,8 @@ __global__ __launch_bounds__(kWave) void candidate_kernel(CandLaunch L) {
     paam_wcrt_opts o = L.o;
     o.full = 1;
     o.util_permille = (int32_t)u;
-    analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr);
+    analyse_set<kSbLds>(bq, o, set, l, s, q.sched - set, q.worst - set, q.worst_R - set, nullptr,
+                        false);
     if (threadIdx.x == 0) {
       const int w = q.worst[0];
       const int64_t wR = q.worst_R[0];
