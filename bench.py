@@ -45,7 +45,7 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "63827a12ed32f09326a152176c84728e42c549d4b2a8be3c7b7c9b6367fa4ec8",
+TRAFFIC = {"sha256": "358c264f134058f76a9ebe14e7c59adf9fc76297a6c38bf5e2dea8764cd4c6b8",
            "bytes_per_launch": 16.05e9, "sets": 1_000_000, "waves_per_cu": 20}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 

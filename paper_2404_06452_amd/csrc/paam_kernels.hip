@@ -303,14 +303,14 @@ __device__ __forceinline__ bool analyse_set(const DevBatch &b, const paam_wcrt_o
   }
   __syncthreads();
 
-  // Verdict mode, sets of up to 64 chains: a first pass with every segment's
-  // handling time at its lower bound A* + same-bucket blocking (the base of
-  // Lemma 2, below each of its iterates) runs the miss check below before
-  // Lemma 2.  Every quantity built from those times only grows with them, so
-  // the check stays a lower bound; a candidate whose miss it proves skips
-  // Lemma 2 and the rest.  Otherwise the tables are cleared and the second
-  // pass runs with the Lemma 2 times.
-  const bool early = !full && C <= kWave;
+  // Verdict mode: a first pass with every segment's handling time at its
+  // lower bound A* + same-bucket blocking (the base of Lemma 2, below each of
+  // its iterates) runs the miss check below before Lemma 2.  Every quantity
+  // built from those times only grows with them, so the check stays a lower
+  // bound; a candidate whose miss it proves skips Lemma 2 and the rest.
+  // Otherwise the tables are cleared and the second pass runs with the
+  // Lemma 2 times.
+  const bool early = !full;
   bool missed = false, early_miss = false;
   for (int pass = early && try_early ? 0 : 1; pass < 2 && !missed; ++pass) {
     if (pass == 0) {
@@ -472,9 +472,10 @@ __device__ __forceinline__ bool analyse_set(const DevBatch &b, const paam_wcrt_o
     //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
     //      a chain whose sum of them passes its deadline proves the miss.
     //      Each sub-chain's sum runs over the ranks, so the check costs about
-    //      as much as a sweep: it pays for sets of up to 64 chains, while for
-    //      larger ones the partial sums of the first sweep find a miss as early ----
-    if (early) {
+    //      as much as a sweep: before Lemma 2 it pays for every set size, after
+    //      it only for sets of up to 64 chains (for larger ones the partial
+    //      sums of the first sweep find a miss as early) ----
+    if (early && (pass == 0 || C <= kWave)) {
       for (int s = lane; s < nrun; s += kWave) {
         const int w = S.info[s];
         const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
