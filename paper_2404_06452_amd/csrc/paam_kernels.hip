@@ -1027,221 +1027,251 @@ __device__ __forceinline__ void analyse_set_q(const DevBatch &b, const paam_wcrt
   }
   __syncthreads();
 
-  // ---- Lemma 2 / Eq. (3): one segment per lane, refilled from the queue
-  //      (the next 64 queue records are loaded one step ahead); a step
-  //      iterates every lane's recurrence up to `micro` times, sharing the
-  //      step's refill and bookkeeping ----
-  {
-    int qnext = 0;
-    bool have = false;
-    int g = 0, rho = 0, a = 0;
-    double hv = 0.0, base = 0.0, capv = 0.0;
-    double2 win = make_double2(0.0, 0.0);
-    if (lane < nseg) win = S.qs[lane];
-    for (int step = 0;; ++step) {
-      const unsigned long long need = __ballot(!have);
-      const int k = (int)__popcll(need & lanes_below());
-      const double wA = __shfl(win.x, k), wP = __shfl(win.y, k);
-      if (!have && qnext + k < nseg) {
-        const int pk = __double2loint(wP);
-        g = __double2hiint(wP);
-        rho = pk & kRankMask;
-        a = pk >> kExecShift;
-        base = wA + L.Bacc[a * C + rho];
-        capv = L.Dd[rho] * capm;
-        hv = 0.0;
-        have = true;
+  // Verdict mode: a first pass with every segment's handling time at its
+  // lower bound A* + same-bucket blocking (below every Lemma 2 iterate) runs
+  // the miss check below before Lemma 2; everything built from those times
+  // only grows with them, so the check stays a lower bound, and a set whose
+  // miss it proves skips Lemma 2 and the rest.  Otherwise the tables and the
+  // Lemma 3 counters are cleared and the second pass runs with Lemma 2.
+  bool missed = false;
+  int maxlev = 0;  // most higher-priority executors of an executor on its core
+  for (int pass = full ? 1 : 0; pass < 2 && !missed; ++pass) {
+    if (pass == 0) {
+      for (int g = lane; g < nseg; g += kWave) {
+        const int a = b.seg_accel[g0 + g];
+        const int rho = L.rank[b.seg_chain[g0 + g]];
+        S.segH[g] = S.segAs[g] + L.Bacc[a * C + rho];
       }
-      qnext += (int)__popcll(need);
-      if (!wave_any(have)) break;
-      if (qnext + lane < nseg) win = S.qs[qnext + lane];
-      if (step >= kMaxIter) {
-        if (lane == 0) L.misc[0] = 1;
-        break;
+      __syncthreads();
+    } else {
+      if (!full) {
+        for (int i = lane; i < X * C; i += kWave) {
+          L.WP[i] = 0.0;
+          L.Pt[i] = 0.0;
+          SB[i] = 0.0;
+        }
+        for (int e = lane; e < X; e += kWave) {
+          L.dfirst[e] = C;
+          L.dspin[e] = 0;
+          L.dmin[e] = 0;
+        }
+        __syncthreads();
       }
-      const int hend = wave_umax(have ? rho : 0);
-      const int klo = min(wave_umin(have ? rho : C), hend);
-      const double *ah = L.Ahat + a * C;
-      bool done = false;
-      for (int it = 0; it < micro; ++it) {
-        double n0 = 0.0, n1 = 0.0;
-        int k2 = 0;
-#pragma unroll 2
-        for (; k2 + 1 < klo; k2 += 2) {
-          const double2 q0 = kr(k2), q1 = kr(k2 + 1);
-          n0 = fma(mu_term(hv, q0.x, q0.y), ah[k2], n0);
-          n1 = fma(mu_term(hv, q1.x, q1.y), ah[k2 + 1], n1);
-        }
-        if (k2 < klo) {
-          const double2 q0 = kr(k2);
-          n0 = fma(mu_term(hv, q0.x, q0.y), ah[k2], n0);
-          ++k2;
-        }
-        for (; k2 + 1 < hend; k2 += 2) {
-          const double2 q0 = kr(k2), q1 = kr(k2 + 1);
-          const double w0 = k2 < rho ? ah[k2] : 0.0;
-          const double w1 = k2 + 1 < rho ? ah[k2 + 1] : 0.0;
-          n0 = fma(mu_term(hv, q0.x, q0.y), w0, n0);
-          n1 = fma(mu_term(hv, q1.x, q1.y), w1, n1);
-        }
-        if (k2 < hend) {
-          const double2 q0 = kr(k2);
-          const double w0 = k2 < rho ? ah[k2] : 0.0;
-          n0 = fma(mu_term(hv, q0.x, q0.y), w0, n0);
-        }
-        if (have && !done) {
-          const double nxt = base + (n0 + n1);
-          if (nxt > capv) {
-            hv = INFINITY;
-            done = true;
-          } else {
-            done = nxt == hv;
-            hv = nxt;
+      // ---- Lemma 2 / Eq. (3): one segment per lane, refilled from the queue
+      //      (the next 64 queue records are loaded one step ahead); a step
+      //      iterates every lane's recurrence up to `micro` times, sharing the
+      //      step's refill and bookkeeping ----
+      {
+        int qnext = 0;
+        bool have = false;
+        int g = 0, rho = 0, a = 0;
+        double hv = 0.0, base = 0.0, capv = 0.0;
+        double2 win = make_double2(0.0, 0.0);
+        if (lane < nseg) win = S.qs[lane];
+        for (int step = 0;; ++step) {
+          const unsigned long long need = __ballot(!have);
+          const int k = (int)__popcll(need & lanes_below());
+          const double wA = __shfl(win.x, k), wP = __shfl(win.y, k);
+          if (!have && qnext + k < nseg) {
+            const int pk = __double2loint(wP);
+            g = __double2hiint(wP);
+            rho = pk & kRankMask;
+            a = pk >> kExecShift;
+            base = wA + L.Bacc[a * C + rho];
+            capv = L.Dd[rho] * capm;
+            hv = 0.0;
+            have = true;
+          }
+          qnext += (int)__popcll(need);
+          if (!wave_any(have)) break;
+          if (qnext + lane < nseg) win = S.qs[qnext + lane];
+          if (step >= kMaxIter) {
+            if (lane == 0) L.misc[0] = 1;
+            break;
+          }
+          const int hend = wave_umax(have ? rho : 0);
+          const int klo = min(wave_umin(have ? rho : C), hend);
+          const double *ah = L.Ahat + a * C;
+          bool done = false;
+          for (int it = 0; it < micro; ++it) {
+            double n0 = 0.0, n1 = 0.0;
+            int k2 = 0;
+    #pragma unroll 2
+            for (; k2 + 1 < klo; k2 += 2) {
+              const double2 q0 = kr(k2), q1 = kr(k2 + 1);
+              n0 = fma(mu_term(hv, q0.x, q0.y), ah[k2], n0);
+              n1 = fma(mu_term(hv, q1.x, q1.y), ah[k2 + 1], n1);
+            }
+            if (k2 < klo) {
+              const double2 q0 = kr(k2);
+              n0 = fma(mu_term(hv, q0.x, q0.y), ah[k2], n0);
+              ++k2;
+            }
+            for (; k2 + 1 < hend; k2 += 2) {
+              const double2 q0 = kr(k2), q1 = kr(k2 + 1);
+              const double w0 = k2 < rho ? ah[k2] : 0.0;
+              const double w1 = k2 + 1 < rho ? ah[k2 + 1] : 0.0;
+              n0 = fma(mu_term(hv, q0.x, q0.y), w0, n0);
+              n1 = fma(mu_term(hv, q1.x, q1.y), w1, n1);
+            }
+            if (k2 < hend) {
+              const double2 q0 = kr(k2);
+              const double w0 = k2 < rho ? ah[k2] : 0.0;
+              n0 = fma(mu_term(hv, q0.x, q0.y), w0, n0);
+            }
+            if (have && !done) {
+              const double nxt = base + (n0 + n1);
+              if (nxt > capv) {
+                hv = INFINITY;
+                done = true;
+              } else {
+                done = nxt == hv;
+                hv = nxt;
+              }
+            }
+            if (!wave_any(have && !done)) break;
+          }
+          if (have && done) {
+            S.segH[g] = hv;
+            have = false;
           }
         }
-        if (!wave_any(have && !done)) break;
       }
-      if (have && done) {
-        S.segH[g] = hv;
-        have = false;
+      __syncthreads();
+    }
+    // ---- sub-chains: own demand, Lemma 2 sum, Lemma 3 constant, overheads,
+    //      and each callback as a blocking candidate ----
+    const bool safe = o.blocking == PAAM_BLOCK_SAFE;
+    for (int s = lane; s < nrun; s += kWave) {
+      const int64_t rr = run0 + s;
+      const int c = b.run_chain[rr];
+      const int e = b.run_exec[rr];
+      const int rho = L.rank[c];
+      double E = 0.0, L2 = 0.0, A0 = 0.0, eps = 0.0, bmax = 0.0;
+      int delta = 0, accm = 0;
+      for (int j = b.run_cb_lo[rr]; j < b.run_cb_hi[rr]; ++j) {
+        const double Ej = scale_time(b.E[cb0 + j], u);
+        E += Ej;
+        double bj = Ej;
+        for (int64_t gg = b.cb_seg_off[cb0 + j]; gg < b.cb_seg_off[cb0 + j + 1]; ++gg) {
+          const int g = (int)(gg - g0);
+          const int a = b.seg_accel[gg];
+          const double Hg = S.segH[g];
+          const double ea = L.aek[2 * a];
+          L2 += Hg;
+          A0 += S.segAs[g] + L.Bacc[a * C + rho];
+          eps += ea;
+          if (safe) bj += Hg + ea;
+          ++delta;
+          accm |= 1 << a;
+        }
+        bmax = fmax(bmax, bj);
+      }
+      atomic_max_nonneg(&SB[e * C + rho], bmax);
+      const bool needL3 =
+          delta > 0 && (o.bound == PAAM_BOUND_L3 || (o.bound == PAAM_BOUND_MIN && delta >= 2));
+      // H* of a sub-chain that does not need Lemma 3 during the iteration (one
+      // segment: Lemma 3 is the recurrence of Lemma 2 and R >= H at the fixed
+      // point, so H* = L2 + eps; no HP request of positive length: Lemma 3 is
+      // the constant A0 <= L2, also at an unbounded window)
+      bool hp_acc = false;
+      for (int a = 0; a < NA; ++a)
+        if (((accm >> a) & 1) && L.misc[1 + a] < rho) hp_acc = true;
+      double hs0 = delta == 0 ? 0.0 : (hp_acc || o.bound == PAAM_BOUND_L2 ? L2 : A0) + eps;
+      if (needL3) {
+        hs0 = 0.0;  // a start below the fixed point
+        atomicMin(&L.dfirst[e], rho);
+        if (L.nrs[rho] >> 16) atomicAdd(&L.dspin[e], 1);
+        atomicAdd(&L.dmin[__popc((uint32_t)L.hpx[e])], 1);  // per level, before the engine
+      }
+      atomicAdd(&L.WP[e * C + rho], E + hs0);
+      atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
+      S.cst[s] = E + (needL3 ? 0.0 : hs0);
+      if (needL3) {  // the Lemma 3 constants are read by these sub-chains only
+        S.L2[s] = L2;
+        S.A0[s] = A0;
+        S.eps[s] = eps;
+      }
+      S.info[s] = rho | (e << kExecShift) | (accm << kAccShift) | (needL3 ? kNeedL3 : 0) |
+                  (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
+    }
+    __syncthreads();
+    // suffix maximum of blocking candidates per executor, lowest priority up
+    // (non-negative doubles order like their bit patterns)
+    for (int e = 0; e < X; ++e) {
+      unsigned long long carry = 0ull;
+      for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
+        const int rho = rb + lane;
+        const unsigned long long v =
+            rho < C ? (unsigned long long)__double_as_longlong(SB[e * C + rho]) : 0ull;
+        unsigned long long incl = wave_suffix_max_u64(v);
+        incl = incl > carry ? incl : carry;
+        if (rho < C) SB[e * C + rho] = __longlong_as_double((long long)incl);
+        carry = __shfl(incl, 0);
       }
     }
-  }
-  __syncthreads();
-
-  // ---- sub-chains: own demand, Lemma 2 sum, Lemma 3 constant, overheads,
-  //      and each callback as a blocking candidate ----
-  const bool safe = o.blocking == PAAM_BLOCK_SAFE;
-  for (int s = lane; s < nrun; s += kWave) {
-    const int64_t rr = run0 + s;
-    const int c = b.run_chain[rr];
-    const int e = b.run_exec[rr];
-    const int rho = L.rank[c];
-    double E = 0.0, L2 = 0.0, A0 = 0.0, eps = 0.0, bmax = 0.0;
-    int delta = 0, accm = 0;
-    for (int j = b.run_cb_lo[rr]; j < b.run_cb_hi[rr]; ++j) {
-      const double Ej = scale_time(b.E[cb0 + j], u);
-      E += Ej;
-      double bj = Ej;
-      for (int64_t gg = b.cb_seg_off[cb0 + j]; gg < b.cb_seg_off[cb0 + j + 1]; ++gg) {
-        const int g = (int)(gg - g0);
-        const int a = b.seg_accel[gg];
-        const double Hg = S.segH[g];
-        const double ea = L.aek[2 * a];
-        L2 += Hg;
-        A0 += S.segAs[g] + L.Bacc[a * C + rho];
-        eps += ea;
-        if (safe) bj += Hg + ea;
-        ++delta;
-        accm |= 1 << a;
-      }
-      bmax = fmax(bmax, bj);
+    for (int e = lane; e < X; e += kWave) {
+      bool blk = false;
+      for (uint32_t mm = (uint32_t)L.hpx[e]; mm; mm &= mm - 1)
+        if (L.dspin[__ffs(mm) - 1] > 0) blk = true;
+      L.dblk[e] = blk ? 1 : 0;
     }
-    atomic_max_nonneg(&SB[e * C + rho], bmax);
-    const bool needL3 =
-        delta > 0 && (o.bound == PAAM_BOUND_L3 || (o.bound == PAAM_BOUND_MIN && delta >= 2));
-    // H* of a sub-chain that does not need Lemma 3 during the iteration (one
-    // segment: Lemma 3 is the recurrence of Lemma 2 and R >= H at the fixed
-    // point, so H* = L2 + eps; no HP request of positive length: Lemma 3 is
-    // the constant A0 <= L2, also at an unbounded window)
-    bool hp_acc = false;
-    for (int a = 0; a < NA; ++a)
-      if (((accm >> a) & 1) && L.misc[1 + a] < rho) hp_acc = true;
-    double hs0 = delta == 0 ? 0.0 : (hp_acc || o.bound == PAAM_BOUND_L2 ? L2 : A0) + eps;
-    if (needL3) {
-      hs0 = 0.0;  // a start below the fixed point
-      atomicMin(&L.dfirst[e], rho);
-      if (L.nrs[rho] >> 16) atomicAdd(&L.dspin[e], 1);
-      atomicAdd(&L.dmin[__popc((uint32_t)L.hpx[e])], 1);  // per level, before the engine
-    }
-    atomicAdd(&L.WP[e * C + rho], E + hs0);
-    atomicAdd(&L.Pt[e * C + rho], E + ((L.nrs[rho] >> 16) ? hs0 : eps));
-    S.cst[s] = E + (needL3 ? 0.0 : hs0);
-    if (needL3) {  // the Lemma 3 constants are read by these sub-chains only
-      S.L2[s] = L2;
-      S.A0[s] = A0;
-      S.eps[s] = eps;
-    }
-    S.info[s] = rho | (e << kExecShift) | (accm << kAccShift) | (needL3 ? kNeedL3 : 0) |
-                (b.hpx_mask[x0 + e] != 0 ? kHasP : 0);
-  }
-  __syncthreads();
-  // suffix maximum of blocking candidates per executor, lowest priority up
-  // (non-negative doubles order like their bit patterns)
-  for (int e = 0; e < X; ++e) {
-    unsigned long long carry = 0ull;
-    for (int rb = ((C - 1) / kWave) * kWave; rb >= 0; rb -= kWave) {
-      const int rho = rb + lane;
-      const unsigned long long v =
-          rho < C ? (unsigned long long)__double_as_longlong(SB[e * C + rho]) : 0ull;
-      unsigned long long incl = wave_suffix_max_u64(v);
-      incl = incl > carry ? incl : carry;
-      if (rho < C) SB[e * C + rho] = __longlong_as_double((long long)incl);
-      carry = __shfl(incl, 0);
-    }
-  }
-  for (int e = lane; e < X; e += kWave) {
-    bool blk = false;
-    for (uint32_t mm = (uint32_t)L.hpx[e]; mm; mm &= mm - 1)
-      if (L.dspin[__ffs(mm) - 1] > 0) blk = true;
-    L.dblk[e] = blk ? 1 : 0;
-  }
-  __syncthreads();
-  for (int s = lane; s < nrun; s += kWave) {
-    const int w = S.info[s];
-    const int rho = w & kRankMask;
-    const int e = (w >> kExecShift) & 31;
-    S.cst[s] += rho + 1 < C ? SB[e * C + rho + 1] : 0.0;
-  }
-  __syncthreads();
-  // hpp weights: Pt[e][h] becomes the sum over the core's higher-priority
-  // executors e2 of E + spin() of h on e2 (so far Pt[e2][h]), and enters
-  // WP[e][h].  Executors are rewritten by decreasing number of
-  // higher-priority executors on their core, so every Pt[e2] read is still
-  // the one accumulated above.
-  int maxlev = 0;
-  for (int e = lane; e < X; e += kWave) maxlev = max(maxlev, __popc((uint32_t)L.hpx[e]));
-  maxlev = wave_umax(maxlev);
-  for (int lev = maxlev; lev >= 1; --lev) {
-    for (int i = lane; i < X * C; i += kWave) {
-      const int e = i / C, h = i - e * C;
-      const uint32_t hm = (uint32_t)L.hpx[e];
-      if (__popc(hm) != lev) continue;
-      double p = 0.0;
-      for (uint32_t m = hm; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
-      L.WP[i] += p;
-      L.Pt[i] = p;
-    }
-    wave_sync();
-  }
-  for (int i = lane; i < X * C; i += kWave)
-    if (L.hpx[i / C] == 0) L.Pt[i] = 0.0;
-
-  __syncthreads();
-
-  // ---- verdict mode: the first iterate of every sub-chain (each interferer
-  //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
-  //      a chain whose sum of them passes its deadline proves the miss ----
-  bool missed = false;
-  if (!full) {
+    __syncthreads();
     for (int s = lane; s < nrun; s += kWave) {
       const int w = S.info[s];
-      const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
-      const double *wp = L.WP + e * C, *pt = L.Pt + e * C;
-      double lb = S.cst[s];
-      for (int h = 0; h < rho; ++h) lb += wp[h];
-      if (w & kHasP)
-        for (int h = rho + 1; h < C; ++h) lb += pt[h];
-      atomicAdd(&L.partial[rho], lb);
+      const int rho = w & kRankMask;
+      const int e = (w >> kExecShift) & 31;
+      S.cst[s] += rho + 1 < C ? SB[e * C + rho + 1] : 0.0;
     }
     __syncthreads();
-    bool miss = false;
-    for (int rho = lane; rho < C; rho += kWave) {
-      if (L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho]) miss = true;
-      L.partial[rho] = 0.0;
+    // hpp weights: Pt[e][h] becomes the sum over the core's higher-priority
+    // executors e2 of E + spin() of h on e2 (so far Pt[e2][h]), and enters
+    // WP[e][h].  Executors are rewritten by decreasing number of
+    // higher-priority executors on their core, so every Pt[e2] read is still
+    // the one accumulated above.
+    maxlev = 0;
+    for (int e = lane; e < X; e += kWave) maxlev = max(maxlev, __popc((uint32_t)L.hpx[e]));
+    maxlev = wave_umax(maxlev);
+    for (int lev = maxlev; lev >= 1; --lev) {
+      for (int i = lane; i < X * C; i += kWave) {
+        const int e = i / C, h = i - e * C;
+        const uint32_t hm = (uint32_t)L.hpx[e];
+        if (__popc(hm) != lev) continue;
+        double p = 0.0;
+        for (uint32_t m = hm; m; m &= m - 1) p += L.Pt[(__ffs(m) - 1) * C + h];
+        L.WP[i] += p;
+        L.Pt[i] = p;
+      }
+      wave_sync();
     }
-    missed = wave_any(miss);
+    for (int i = lane; i < X * C; i += kWave)
+      if (L.hpx[i / C] == 0) L.Pt[i] = 0.0;
+
     __syncthreads();
+
+    // ---- verdict mode: the first iterate of every sub-chain (each interferer
+    //      counted once, a Lemma 3 sub-chain without its H*) is a lower bound;
+    //      a chain whose sum of them passes its deadline proves the miss ----
+    if (!full) {
+      for (int s = lane; s < nrun; s += kWave) {
+        const int w = S.info[s];
+        const int rho = w & kRankMask, e = (w >> kExecShift) & 31;
+        const double *wp = L.WP + e * C, *pt = L.Pt + e * C;
+        double lb = S.cst[s];
+        for (int h = 0; h < rho; ++h) lb += wp[h];
+        if (w & kHasP)
+          for (int h = rho + 1; h < C; ++h) lb += pt[h];
+        atomicAdd(&L.partial[rho], lb);
+      }
+      __syncthreads();
+      bool miss = false;
+      for (int rho = lane; rho < C; rho += kWave) {
+        if (L.partial[rho] + (double)((L.nrs[rho] & 0xffff) - 1) * hop > L.Dd[rho]) miss = true;
+        L.partial[rho] = 0.0;
+      }
+      missed = wave_any(miss);
+      __syncthreads();
+    }
   }
 
   // ---- the queue of sub-chains: the Lemma 3 sub-chains first, each after
