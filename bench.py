@@ -45,8 +45,8 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "358c264f134058f76a9ebe14e7c59adf9fc76297a6c38bf5e2dea8764cd4c6b8",
-           "bytes_per_launch": 16.05e9, "sets": 1_000_000, "waves_per_cu": 20}
+TRAFFIC = {"sha256": "8733d1ca24b06bfa01049cf039f3c2e5a057c821993e1292c651472a12677280",
+           "bytes_per_launch": 15.56e9, "sets": 1_000_000, "waves_per_cu": 20}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
