@@ -890,7 +890,7 @@ __device__ __forceinline__ double pack2(int hi, int lo) { return __hiloint2doubl
 // final; until then it is re-evaluated with the current weights.  Every
 // iterate stays below the least fixed point (the system is monotone and
 // starts at 0), so the final values are the least fixed points.
-template <class KR, bool kSbLds>
+template <class KR, bool kSbLds, bool kFull>
 __device__ __forceinline__ void analyse_set_q(const DevBatch &b, const paam_wcrt_opts &o,
                                               int64_t set, KR kr, Lds &L, Scratch &S,
                                               int8_t *set_sched, int32_t *set_worst,
@@ -908,7 +908,7 @@ __device__ __forceinline__ void analyse_set_q(const DevBatch &b, const paam_wcrt
   const int64_t run0 = b.set_run_off[set];
   const int nrun = (int)(b.set_run_off[set + 1] - run0);
   const int32_t u = o.util_permille;
-  const bool full = o.full != 0;
+  constexpr bool full = kFull;  // the launch picks the instantiation by the option
   const double hop = (double)b.eps_hop[set];
   const double capm = (double)o.cap_mult;
   const bool uploaded = KR::kUploaded;
@@ -1615,6 +1615,9 @@ __global__ void reset_counter(unsigned long long *counter) { *counter = 0ull; }
 // The analysis under the uploaded priorities: the (2T-1, 1/T) table is read
 // from the arena, the blocking table lives in the wave's global scratch, so a
 // wave needs only the LDS tables of the iteration.
+// Instantiated per mode: every chain's bound (kFull) or the verdict alone,
+// so each compiles without the other's code.
+template <bool kFull>
 __global__ __launch_bounds__(kWave, 5) void wcrt_kernel(WcrtLaunch L) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   Lds l = carve_lds(lds_raw, L.b.max_C, L.b.max_X, L.b.max_NA > 0 ? L.b.max_NA : 1, false, false);
@@ -1635,7 +1638,7 @@ __global__ __launch_bounds__(kWave, 5) void wcrt_kernel(WcrtLaunch L) {
     const int64_t set = L.b.work_order[i];
     const int64_t c0 = L.b.set_chain_off[set];
     KRConst kr{(const __attribute__((address_space(4))) double *)(L.b.KRr + 2 * c0)};
-    analyse_set_q<KRConst, false>(L.b, L.o, set, kr, l, s, L.set_sched, L.set_worst,
+    analyse_set_q<KRConst, false, kFull>(L.b, L.o, set, kr, l, s, L.set_sched, L.set_worst,
                                    L.set_worst_R, L.chain_R, L.micro);
   }
 }
@@ -1934,7 +1937,10 @@ int launch_wcrt(const WcrtLaunch &L, void *stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   if (L.b.n_sets == 0) return 0;
-  hipLaunchKernelGGL(wcrt_kernel, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  if (L.o.full)
+    hipLaunchKernelGGL(wcrt_kernel<true>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
+  else
+    hipLaunchKernelGGL(wcrt_kernel<false>, dim3(L.grid), dim3(kWave), L.lds_bytes, st, L);
   return (int)hipGetLastError();
 }
 
