@@ -45,8 +45,8 @@ def log(msg):
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the
 # counters' reading for the 1 GiB calibration copy.  Valid only for the kernel
 # source with this SHA-256 at the same waves per CU; null otherwise.
-TRAFFIC = {"sha256": "8733d1ca24b06bfa01049cf039f3c2e5a057c821993e1292c651472a12677280",
-           "bytes_per_launch": 15.56e9, "sets": 1_000_000, "waves_per_cu": 20}
+TRAFFIC = {"sha256": "94161b1f2453528e5ca1baf49a5ac98bcecad7047e3371d4b8d5daf3bb6f1e9d",
+           "bytes_per_launch": 16.11e9, "sets": 1_000_000, "waves_per_cu": 20}
 KERNEL_SRC = os.path.join(ROOT, "paper_2404_06452_amd", "csrc", "paam_kernels.hip")
 
 COPY_BYTES = 1 << 30
