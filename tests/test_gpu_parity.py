@@ -188,3 +188,29 @@ def test_autotune_picks_a_candidate_and_keeps_results():
     _paam.paam_wcrt_batch(dev, o, out, ws2)
     torch.cuda.synchronize()
     assert np.array_equal(out.chain_R.cpu().numpy()[:cs.n_chains], r["chain_R"])
+
+
+@pytest.mark.gpu
+def test_verdict_mode_equals_full_mode_verdicts_at_scale(paam):
+    # Verdict mode stops a set at its first proven miss: lower bounds checked
+    # before Lemma 2 (segments at A* + same-bucket blocking) and before the
+    # iteration.  Its verdict must equal the full analysis's on every set, on
+    # the sweep workload (4-64 chains) at low, middle and high levels, and on
+    # the search sets, whose uploaded order is candidate 0 of a search (the
+    # search's sweep analysis, with the same checks, against the full
+    # analysis of the queue-driven engine).
+    cs = chaingen.generate("sweep", 60_000)
+    dev = paam.Chainset(cs, device="cuda:0")
+    for u in (100, 300, 550, 950):
+        note("sweep verdicts at %d" % u)
+        f = paam.wcrt(dev, full=True, util_permille=u)
+        v = paam.wcrt(dev, full=False, util_permille=u)
+        assert np.array_equal(f["sched"], v["sched"]), u
+        assert 0 < int(np.sum(f["sched"] == 0)) and (u > 300 or int(np.sum(f["sched"] == 1)) > 0)
+    cs = chaingen.generate("search", 20_000)
+    dev = paam.Chainset(cs, device="cuda:0")
+    for u in (50, 200, 1000):
+        note("search-set verdicts at %d" % u)
+        f = paam.wcrt(dev, full=True, util_permille=u)
+        g = paam.search(dev, 1, 7, util_permille=u)
+        assert np.array_equal(g["found"] == 0, f["sched"] == 1), u
